@@ -1,0 +1,167 @@
+"""Benchmark of the GL history-sum hot path on one MI355X.
+
+Workload: 2D 256 x 256 grid, gamma 0.8, alpha 1, f = -0.1 u, Gaussian bump
+sigma 0.1 plus seeded uniform noise (seed 2), r = 0.1, 20000 steps, full
+memory.  One benchmark step is one whole solve (restart from u0, 20000 time
+steps, each summing every stored state), with the inputs resident in device
+memory.  The metric is history MACs/s: one MAC is one (weight x stored state)
+term of a history sum, counted once per grid point.
+
+Prints one JSON line.  Also reports, for each history-sum path, the relative
+L2 error against the FP64 oracle on an 800-step prefix of the same workload,
+the mode-by-mode error at full length (the workload is linear, so single
+sine modes are sampled outputs the oracle computes exactly), the per-kernel
+durations from HIP events, and the oracle's own throughput on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
+BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix, TFLOP/s
+PREFIX_STEPS = 800           # oracle sample: the first 800 steps of the workload
+MODES = [(1, 1), (1, 3), (3, 1), (3, 3), (1, 5), (5, 5)]
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def modal(u, p, modes):
+    from paper_1004_5128_amd import workloads as W
+    x, y = W.coords(p["nx"]), W.coords(p["ny"])
+    U = np.asarray(u).reshape(p["ny"], p["nx"])
+    return np.array([4.0 / ((p["nx"] + 1) * (p["ny"] + 1)) *
+                     (np.sin(b * np.pi * y) @ U @ np.sin(a * np.pi * x)) for a, b in modes])
+
+
+def run_path(path, w, steps, warmup, block_B):
+    import torch
+    from paper_1004_5128_amd import gl
+    p, n = w["problem"], w["nsteps"]
+    P = gl.npoints(p)
+    u0 = torch.as_tensor(w["u0"], dtype=torch.float64).cuda()
+    s = gl.Solver(p, w["memory"], u0, max_steps=n, sum_path=path, block_B=block_B)
+    macs = P * sum(s.schedule_terms(k) for k in range(n))
+    gemv_bytes = 4 * P * sum(s.schedule_terms(k) - 1 for k in range(n))
+    for i in range(warmup):
+        log(path, "warmup", i)
+        s.reset(u0)
+        s.advance(n)
+    torch.cuda.synchronize()
+    s.set_profiling(True)
+    log(path, "timed", steps)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.reset(u0)
+        s.advance(n)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = s.profile()
+    s.set_profiling(False)
+    uT = s.state().cpu().numpy()
+    # prefix run for the oracle comparison
+    s.reset(u0)
+    s.advance(PREFIX_STEPS)
+    u_prefix = s.state().cpu().numpy()
+    s.close()
+    ms = (t1 - t0) * 1e3 / steps
+    return {"ms_per_step": ms, "macs": macs, "gemv_bytes": gemv_bytes, "prof": prof, "uT": uT,
+            "u_prefix": u_prefix, "steps": steps}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--paths", default="gemv")
+    ap.add_argument("--block-B", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (the solver runs on a single "
+              "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1004_5128_amd import workloads as W
+    torch.cuda.set_device(0)
+    w = W.cfg2()
+    p, n = w["problem"], w["nsteps"]
+    P = W.npoints(p)
+
+    paths = [x for x in args.paths.split(",") if x]
+    res = {path: run_path(path, w, args.steps, args.warmup, args.block_B) for path in paths}
+    primary = paths[-1]
+
+    out_paths = {}
+    oracle_prefix = oracle_modal = None
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("oracle prefix", PREFIX_STEPS, "steps on", oracle.num_threads(), "threads")
+        t0 = time.perf_counter()
+        oracle_prefix = oracle.run(p, w["memory"], w["u0"], PREFIX_STEPS)
+        t_cpu = time.perf_counter() - t0
+        macs_cpu = P * PREFIX_STEPS * (PREFIX_STEPS + 1) // 2
+        cpu = {"value": macs_cpu / t_cpu, "unit": "history MACs/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "first %d of the %d steps of the same 256x256 workload (%.3g MACs, "
+                         "%.1f s)" % (PREFIX_STEPS, n, macs_cpu, t_cpu)}
+        c0 = modal(w["u0"], p, MODES)
+        oracle_modal = np.array([c0[i] * oracle.mode_run(p, w["memory"], a, b, 1.0, n)[-1]
+                                 for i, (a, b) in enumerate(MODES)])
+
+    for path, r in res.items():
+        d = {"ms_per_step": r["ms_per_step"], "value": r["macs"] / (r["ms_per_step"] / 1e3)}
+        for name, (cnt, ms) in r["prof"].items():
+            if cnt:
+                d.setdefault("kernels", {})[name] = {"launches": cnt // r["steps"],
+                                                     "ms_per_solve": ms / r["steps"],
+                                                     "avg_us": ms * 1e3 / cnt}
+        if oracle_prefix is not None:
+            d["rel_l2_vs_oracle_prefix"] = float(np.linalg.norm(r["u_prefix"] - oracle_prefix) /
+                                                 np.linalg.norm(oracle_prefix))
+            cg = modal(r["uT"], p, MODES)
+            d["modal_err_vs_oracle_full_length"] = float(np.abs(cg - oracle_modal).max() /
+                                                         np.abs(oracle_modal).max())
+        out_paths[path] = d
+
+    r = res[primary]
+    prof = r["prof"]
+    roofline = None
+    if primary == "gemv":
+        cnt, ms = prof["hist_gemv"]
+        bytes_per_launch = r["gemv_bytes"] * r["steps"] / cnt
+        achieved = bytes_per_launch / (ms / cnt * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "hist_gemv_kernel", "achieved": achieved,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": None, "avg_launch_us": ms * 1e3 / cnt,
+                    "algorithmic_bytes_per_launch": bytes_per_launch}
+    value = r["macs"] / (r["ms_per_step"] / 1e3)
+    line = {
+        "metric": "history MACs/s + rel-L2 vs FP64 oracle; plain FP32 sum vs blocked MFMA sum",
+        "value": value, "unit": "history MACs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 history, f64 accumulate",
+        "data": "synthetic",
+        "config": {"workload": "2d_256x256_gamma0.8_alpha1_linear0.1_gaussian_r0.1_20000steps_full",
+                   "grid": [p["nx"], p["ny"]], "time_steps": n, "memory": "full",
+                   "history_macs_per_solve": r["macs"], "path": primary},
+        "paths": out_paths,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,441 @@
+// C ABI of libgl (include/gl.h): context lifetime, validation, device memory,
+// and the step driver that sequences the history-sum and update kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "gl.h"
+#include "gl_internal.h"
+
+struct gl_ctx {
+    std::vector<gl::Problem> probs;
+    gl_options opt{};
+    hipStream_t stream = nullptr;
+    int64_t k = 0;             // steps taken
+    int64_t total_points = 0;  // sum of problem points
+    gl::Schedule sched;
+    gl::Run *d_runs = nullptr;
+    double *partial = nullptr;  // kMaxSplits x max P (FP64)
+    int *d_flag = nullptr;
+    std::vector<void *> allocs;
+    std::string err;
+    // profiling: events bracketing timed kernel launches, resolved at sync points
+    bool prof = false;
+    std::vector<hipEvent_t> event_pool;
+    struct Pending {
+        int kernel;
+        hipEvent_t start, stop;
+    };
+    std::vector<Pending> pending;
+    int64_t prof_launches[GL_KERNEL_COUNT] = {};
+    double prof_ms[GL_KERNEL_COUNT] = {};
+};
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+gl_status load_initial(gl_ctx *ctx, const double *u0);
+
+gl_status fail(gl_ctx *ctx, gl_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx)
+        ctx->err = buf;
+    else
+        g_thread_err = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                      \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((ctx), GL_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+    } while (0)
+
+template <class T>
+gl_status dev_alloc(gl_ctx *ctx, T **ptr, size_t count) {
+    void *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, GL_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    ctx->allocs.push_back(p);
+    *ptr = static_cast<T *>(p);
+    return GL_OK;
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+gl_status validate(const gl_problem *probs, int32_t nprob, const gl_options *opt,
+                   const double *u0, gl_ctx **out) {
+    if (!out) return fail(nullptr, GL_EINVAL, "gl_init: out is NULL");
+    *out = nullptr;
+    if (!probs || nprob < 1) return fail(nullptr, GL_EINVAL, "gl_init: need nprob >= 1 problems");
+    if (!opt) return fail(nullptr, GL_EINVAL, "gl_init: options are NULL");
+    if (!u0) return fail(nullptr, GL_EINVAL, "gl_init: u0 is NULL");
+    if (opt->mem_mode < GL_MEM_FULL || opt->mem_mode > GL_MEM_ADAPTIVE)
+        return fail(nullptr, GL_EINVAL, "gl_init: unknown mem_mode %d", opt->mem_mode);
+    if (opt->mem_mode == GL_MEM_SHORT && opt->short_L < 0)
+        return fail(nullptr, GL_EINVAL, "gl_init: short_L must be >= 0");
+    if (opt->mem_mode == GL_MEM_ADAPTIVE) {
+        if (opt->adapt_a < 2) return fail(nullptr, GL_EINVAL, "gl_init: adapt_a must be >= 2");
+        if (opt->adapt_rule < GL_ADAPT_PARTITION || opt->adapt_rule > GL_ADAPT_UNIT_STRIDE)
+            return fail(nullptr, GL_EINVAL, "gl_init: unknown adapt_rule %d", opt->adapt_rule);
+    }
+    if (opt->sum_path != GL_SUM_GEMV_FP32 && opt->sum_path != GL_SUM_TOEPLITZ_BF16X3)
+        return fail(nullptr, GL_EINVAL, "gl_init: unknown sum_path %d", opt->sum_path);
+    if (opt->max_steps < 1 || opt->max_steps > (int64_t)INT32_MAX / 2)
+        return fail(nullptr, GL_EINVAL, "gl_init: max_steps must be in [1, 2^30]");
+    if (opt->ckpt_every < 0) return fail(nullptr, GL_EINVAL, "gl_init: ckpt_every must be >= 0");
+    for (int32_t i = 0; i < nprob; ++i) {
+        const gl_problem &p = probs[i];
+        if (p.ndim != 1 && p.ndim != 2)
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: ndim must be 1 or 2", i);
+        if (p.nx < 1 || (p.ndim == 2 && p.ny < 1))
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: grid must have >= 1 point", i);
+        if (!(p.dx > 0) || !std::isfinite(p.dx) || !(p.dt > 0) || !std::isfinite(p.dt))
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: dx and dt must be > 0", i);
+        if (!(p.gamma > 0.0 && p.gamma <= 1.0))
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: gamma must be in (0, 1]", i);
+        if (!(p.alpha > 0.0) || !std::isfinite(p.alpha))
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: alpha must be > 0", i);
+        if (p.rxn < GL_RXN_NONE || p.rxn > GL_RXN_FISHER || !std::isfinite(p.rxn_rate))
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: bad reaction", i);
+        const double r = p.alpha * std::pow(p.dt, p.gamma) / (p.dx * p.dx);
+        // von Neumann bound of the explicit scheme: the highest grid mode has
+        // Lap eigenvalue -> -4 ndim, and sum psi (-1)^m = 2^(1 - gamma).
+        if (r * 4.0 * p.ndim > std::pow(2.0, p.gamma) * (1.0 + 1e-12))
+            return fail(nullptr, GL_EUNSTABLE,
+                        "gl_init: problem %d: r = %.6g exceeds the stability bound 2^gamma/(4 "
+                        "ndim) = %.6g",
+                        i, r, std::pow(2.0, p.gamma) / (4.0 * p.ndim));
+    }
+    return GL_OK;
+}
+
+gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const double *u0) {
+    const gl_options &opt = ctx->opt;
+    const int64_t rows = opt.max_steps + 1;
+
+    // capacity: history arena + tables + state
+    size_t need = 0;
+    int64_t maxP = 0;
+    ctx->probs.resize(nprob);
+    for (int32_t i = 0; i < nprob; ++i) {
+        gl::Problem &pb = ctx->probs[i];
+        pb.p = probs[i];
+        if (pb.p.ndim == 1) pb.p.ny = 1;
+        pb.P = (int64_t)pb.p.nx * pb.p.ny;
+        pb.ld = round_up(pb.P, 64);
+        pb.r = pb.p.alpha * std::pow(pb.p.dt, pb.p.gamma) / (pb.p.dx * pb.p.dx);
+        pb.offset = ctx->total_points;
+        ctx->total_points += pb.P;
+        if (pb.P > maxP) maxP = pb.P;
+        need += (size_t)rows * pb.ld * sizeof(float) + 2 * (size_t)rows * sizeof(double) +
+                2 * (size_t)pb.P * sizeof(double);
+    }
+    need += (size_t)gl::kMaxSplits * maxP * sizeof(double);
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
+    if (need + (size_t)(256u << 20) > free_b)
+        return fail(ctx, GL_ENOMEM, "gl_init: need %.3f GB of device memory, %.3f GB free",
+                    need / 1e9, free_b / 1e9);
+
+    ctx->sched = gl::build_schedule(opt, opt.max_steps);
+    gl_status st;
+    if ((st = dev_alloc(ctx, &ctx->d_runs, ctx->sched.runs.size()))) return st;
+    HIP_TRY(ctx, hipMemcpy(ctx->d_runs, ctx->sched.runs.data(),
+                           ctx->sched.runs.size() * sizeof(gl::Run), hipMemcpyHostToDevice));
+    if ((st = dev_alloc(ctx, &ctx->partial, (size_t)gl::kMaxSplits * maxP))) return st;
+    if ((st = dev_alloc(ctx, &ctx->d_flag, 1))) return st;
+
+    for (gl::Problem &pb : ctx->probs) {
+        if ((st = dev_alloc(ctx, &pb.psi, rows))) return st;
+        if ((st = dev_alloc(ctx, &pb.dpsi, rows))) return st;
+        if ((st = dev_alloc(ctx, &pb.H, (size_t)rows * pb.ld))) return st;
+        if ((st = dev_alloc(ctx, &pb.u[0], pb.P))) return st;
+        if ((st = dev_alloc(ctx, &pb.u[1], pb.P))) return st;
+        gl::launch_weights(pb.p.gamma, opt.max_steps, pb.psi, pb.dpsi, ctx->stream);
+        HIP_TRY(ctx, hipGetLastError());
+    }
+    return load_initial(ctx, u0);
+}
+
+void release(gl_ctx *ctx) {
+    for (void *p : ctx->allocs) (void)hipFree(p);
+    ctx->allocs.clear();
+    for (auto &pd : ctx->pending) {
+        ctx->event_pool.push_back(pd.start);
+        ctx->event_pool.push_back(pd.stop);
+    }
+    ctx->pending.clear();
+    for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+    ctx->event_pool.clear();
+}
+
+gl_status take_event(gl_ctx *ctx, hipEvent_t *ev) {
+    if (ctx->event_pool.empty()) {
+        HIP_TRY(ctx, hipEventCreate(ev));
+    } else {
+        *ev = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+    }
+    return GL_OK;
+}
+
+// Adds the durations of the pending event pairs (the stream must be synchronised).
+gl_status resolve_profile(gl_ctx *ctx) {
+    for (auto &pd : ctx->pending) {
+        float ms = 0.f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, pd.start, pd.stop));
+        ctx->prof_ms[pd.kernel] += ms;
+        ctx->prof_launches[pd.kernel] += 1;
+        ctx->event_pool.push_back(pd.start);
+        ctx->event_pool.push_back(pd.stop);
+    }
+    ctx->pending.clear();
+    return GL_OK;
+}
+
+// Runs launch() and, in profiling mode, brackets it with events on the stream.
+template <class F>
+gl_status timed(gl_ctx *ctx, int kernel, F &&launch) {
+    if (!ctx->prof) {
+        launch();
+        return GL_OK;
+    }
+    gl_ctx::Pending pd{kernel, nullptr, nullptr};
+    gl_status st;
+    if ((st = take_event(ctx, &pd.start)) || (st = take_event(ctx, &pd.stop))) return st;
+    HIP_TRY(ctx, hipEventRecord(pd.start, ctx->stream));
+    launch();
+    HIP_TRY(ctx, hipEventRecord(pd.stop, ctx->stream));
+    ctx->pending.push_back(pd);
+    if (ctx->pending.size() >= 4096) {
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        return resolve_profile(ctx);
+    }
+    return GL_OK;
+}
+
+// Starts every problem from u0 at k = 0 and checks u0 is finite.
+gl_status load_initial(gl_ctx *ctx, const double *u0) {
+    for (gl::Problem &pb : ctx->probs) {
+        pb.cur = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(pb.u[0], u0 + pb.offset, pb.P * sizeof(double),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        gl::launch_to_float(pb.u[0], pb.H, pb.P, ctx->stream);
+        HIP_TRY(ctx, hipGetLastError());
+    }
+    ctx->k = 0;
+    HIP_TRY(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
+    for (gl::Problem &pb : ctx->probs) gl::launch_check_finite(pb.u[0], pb.P, ctx->d_flag, ctx->stream);
+    int flag = 0;
+    HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    if (flag) return fail(ctx, GL_ENONFINITE, "u0 holds NaN or Inf");
+    return GL_OK;
+}
+
+// One step k -> k + 1 of every problem on the plain GEMV path.
+gl_status step_gemv(gl_ctx *ctx) {
+    const int64_t k = ctx->k;
+    const int64_t rb = ctx->sched.run_begin[k];
+    const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
+    const int64_t T = ctx->sched.terms[k];
+    for (gl::Problem &pb : ctx->probs) {
+        const double *u = pb.u[pb.cur];
+        double *un = pb.u[pb.cur ^ 1];
+        // term 0 is (m = 0, coef 1): psi(0) u[k] = u[k] comes from the FP64 state
+        const int nsplit = gl::gemv_splits(T - 1, pb.P);
+        gl_status st;
+        if (nsplit > 0) {
+            st = timed(ctx, GL_KERNEL_HIST_GEMV, [&] {
+                gl::launch_hist_gemv(pb.H, pb.ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 1, T,
+                                     nsplit, ctx->partial, ctx->stream);
+            });
+            if (st != GL_OK) return st;
+        }
+        st = timed(ctx, GL_KERNEL_UPDATE, [&] {
+            gl::launch_update(pb, u, un, pb.H + (k + 1) * pb.ld, ctx->partial, nsplit, ctx->stream);
+        });
+        if (st != GL_OK) return st;
+        pb.cur ^= 1;
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    ctx->k = k + 1;
+    return GL_OK;
+}
+
+gl_status copy_state(gl_ctx *ctx, double *dst) {
+    for (gl::Problem &pb : ctx->probs)
+        HIP_TRY(ctx, hipMemcpyAsync(dst + pb.offset, pb.u[pb.cur], pb.P * sizeof(double),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    return GL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gl_status gl_init(const gl_problem *probs, int32_t nprob, const gl_options *opt, const double *u0,
+                  gl_ctx **out) {
+    gl_status st = validate(probs, nprob, opt, u0, out);
+    if (st != GL_OK) return st;
+    if (opt->sum_path == GL_SUM_TOEPLITZ_BF16X3)
+        return fail(nullptr, GL_EUNSUPPORTED, "gl_init: the Toeplitz path is not built yet");
+    std::unique_ptr<gl_ctx> ctx(new gl_ctx);
+    ctx->opt = *opt;
+    ctx->stream = static_cast<hipStream_t>(opt->stream);
+    st = init_impl(ctx.get(), probs, nprob, u0);
+    if (st != GL_OK) {
+        g_thread_err = ctx->err;
+        (void)hipStreamSynchronize(ctx->stream);
+        release(ctx.get());
+        return st;
+    }
+    *out = ctx.release();
+    return GL_OK;
+}
+
+gl_status gl_step_n(gl_ctx *ctx, int64_t n, double *uT) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_step_n: ctx is NULL");
+    if (n < 0) return fail(ctx, GL_EINVAL, "gl_step_n: n must be >= 0");
+    if (ctx->k + n > ctx->opt.max_steps)
+        return fail(ctx, GL_ECAPACITY, "gl_step_n: %lld + %lld steps exceed max_steps = %lld",
+                    (long long)ctx->k, (long long)n, (long long)ctx->opt.max_steps);
+    gl_status st;
+    for (int64_t s = 0; s < n; ++s)
+        if ((st = step_gemv(ctx)) != GL_OK) return st;
+    if (uT && (st = copy_state(ctx, uT)) != GL_OK) return st;
+    if (ctx->opt.check_finite) {
+        HIP_TRY(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
+        for (gl::Problem &pb : ctx->probs)
+            gl::launch_check_finite(pb.u[pb.cur], pb.P, ctx->d_flag, ctx->stream);
+        int flag = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost,
+                                    ctx->stream));
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (flag) return fail(ctx, GL_ENONFINITE, "gl_step_n: state holds NaN or Inf at step %lld",
+                              (long long)ctx->k);
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return resolve_profile(ctx);
+}
+
+gl_status gl_reset(gl_ctx *ctx, const double *u0) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_reset: ctx is NULL");
+    if (!u0) return fail(ctx, GL_EINVAL, "gl_reset: u0 is NULL");
+    return load_initial(ctx, u0);
+}
+
+gl_status gl_set_profiling(gl_ctx *ctx, int32_t on) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_set_profiling: ctx is NULL");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    gl_status st = resolve_profile(ctx);
+    if (st != GL_OK) return st;
+    ctx->prof = on != 0;
+    for (int i = 0; i < GL_KERNEL_COUNT; ++i) {
+        ctx->prof_launches[i] = 0;
+        ctx->prof_ms[i] = 0.0;
+    }
+    return GL_OK;
+}
+
+gl_status gl_profile(gl_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_profile: ctx is NULL");
+    if (kernel < 0 || kernel >= GL_KERNEL_COUNT || !launches || !total_ms)
+        return fail(ctx, GL_EINVAL, "gl_profile: bad kernel id or NULL output");
+    *launches = ctx->prof_launches[kernel];
+    *total_ms = ctx->prof_ms[kernel];
+    return GL_OK;
+}
+
+gl_status gl_adjoint(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *dparams) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_adjoint: ctx is NULL");
+    if (!dL_duT || !dL_du0 || !dparams) return fail(ctx, GL_EINVAL, "gl_adjoint: NULL argument");
+    if (ctx->k < 1) return fail(ctx, GL_ESTATE, "gl_adjoint: no forward step taken");
+    return fail(ctx, GL_EUNSUPPORTED, "gl_adjoint: not built yet");
+}
+
+void gl_free(gl_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    release(ctx);
+    delete ctx;
+}
+
+const char *gl_last_error(const gl_ctx *ctx) {
+    return ctx ? ctx->err.c_str() : g_thread_err.c_str();
+}
+
+int64_t gl_steps_done(const gl_ctx *ctx) { return ctx ? ctx->k : -1; }
+
+gl_status gl_get_state(gl_ctx *ctx, double *u) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_get_state: ctx is NULL");
+    if (!u) return fail(ctx, GL_EINVAL, "gl_get_state: u is NULL");
+    gl_status st = copy_state(ctx, u);
+    if (st != GL_OK) return st;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return GL_OK;
+}
+
+gl_status gl_get_weights(gl_ctx *ctx, int32_t iprob, int64_t count, double *psi, double *dpsi) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_get_weights: ctx is NULL");
+    if (iprob < 0 || iprob >= (int32_t)ctx->probs.size() || count < 0 ||
+        count > ctx->opt.max_steps + 1)
+        return fail(ctx, GL_EINVAL, "gl_get_weights: bad problem index or count");
+    const gl::Problem &pb = ctx->probs[iprob];
+    if (psi)
+        HIP_TRY(ctx, hipMemcpyAsync(psi, pb.psi, count * sizeof(double), hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+    if (dpsi)
+        HIP_TRY(ctx, hipMemcpyAsync(dpsi, pb.dpsi, count * sizeof(double),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return GL_OK;
+}
+
+int64_t gl_schedule_terms(const gl_ctx *ctx, int64_t k) {
+    if (!ctx || k < 0 || k > ctx->opt.max_steps) return -1;
+    return ctx->sched.terms[k];
+}
+
+gl_status gl_history_sum(gl_ctx *ctx, int32_t iprob, int64_t k, const float *hist, int64_t ld,
+                         double *S) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_history_sum: ctx is NULL");
+    if (iprob < 0 || iprob >= (int32_t)ctx->probs.size())
+        return fail(ctx, GL_EINVAL, "gl_history_sum: bad problem index");
+    const gl::Problem &pb = ctx->probs[iprob];
+    if (!hist || !S) return fail(ctx, GL_EINVAL, "gl_history_sum: NULL argument");
+    if (k < 0 || k > ctx->opt.max_steps)
+        return fail(ctx, GL_EINVAL, "gl_history_sum: k out of [0, max_steps]");
+    if (ld < pb.P || ld % 4 != 0 || (reinterpret_cast<uintptr_t>(hist) & 15u) != 0)
+        return fail(ctx, GL_EINVAL, "gl_history_sum: need ld >= P, ld %% 4 == 0, 16-byte aligned");
+    const int64_t rb = ctx->sched.run_begin[k];
+    const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
+    const int64_t T = ctx->sched.terms[k];
+    const int nsplit = gl::gemv_splits(T, pb.P);
+    gl::launch_hist_gemv(hist, ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 0, T, nsplit,
+                         ctx->partial, ctx->stream);
+    gl::launch_reduce_partials(ctx->partial, nsplit, pb.P, nullptr, S, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return GL_OK;
+}
+
+}  // extern "C"

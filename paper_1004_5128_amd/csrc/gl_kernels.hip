@@ -1,0 +1,271 @@
+// HIP kernels of the plain history-sum path for gfx950 (CDNA4, wave64):
+// GL weights, the history GEMV, the stencil + reaction update and helpers.
+#include <hip/hip_runtime.h>
+
+#include "gl_internal.h"
+
+namespace gl {
+
+// ------------------------------------------------------------------ weights
+//
+// psi(gamma, m) = (-1)^m binom(1 - gamma, m) (Sec. 2.1, eq. (8)) by the
+// recurrence of eq. (11) written as psi(m) = psi(m-1) (m - 2 + gamma) / m from
+// psi(0) = 1 (eq. (12)), and its gamma-derivative by differentiating the same
+// product: psi'(m) = psi'(m-1) (m - 2 + gamma) / m + psi(m-1) / m.  A single
+// lane walks the recurrence; it runs once per context.
+__global__ void weights_kernel(double gamma, int64_t n, double *__restrict__ psi,
+                               double *__restrict__ dpsi) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double w = 1.0, dw = 0.0;
+    psi[0] = w;
+    dpsi[0] = dw;
+    for (int64_t m = 1; m <= n; ++m) {
+        const double inv_m = 1.0 / (double)m;
+        const double ratio = ((double)m - 2.0 + gamma) * inv_m;
+        const double dnext = dw * ratio + w * inv_m;
+        w = w * ratio;
+        dw = dnext;
+        psi[m] = w;
+        dpsi[m] = dw;
+    }
+}
+
+void launch_weights(double gamma, int64_t n, double *psi, double *dpsi, hipStream_t s) {
+    hipLaunchKernelGGL(weights_kernel, dim3(1), dim3(64), 0, s, gamma, n, psi, dpsi);
+}
+
+// ------------------------------------------------------------ history GEMV
+//
+// Each step's sum sum_t coef_t psi(m_t) H[k - m_t, p] is a weighted reduction
+// of whole history rows: a GEMV with a row-major [rows x P] FP32 matrix.  It
+// is HBM-bound (4 bytes per multiply-add), so the kernel streams rows with
+// 16-byte loads, 1 KB per wave per row, and keeps several rows in flight per
+// lane.  A workgroup of 256 lanes owns 1024 consecutive points; the terms are
+// split into gridDim.y contiguous ranges (split-K) so that small grids still
+// fill the 256 CUs.  Weights are wave-uniform (scalar loads) and the
+// accumulation is FP64 in term order: results are deterministic and depend only
+// on the term sequence, the term range and the split count.
+
+constexpr int kGemvThreads = 256;
+constexpr int kGemvUnroll = 8;
+
+__global__ __launch_bounds__(kGemvThreads) void hist_gemv_kernel(
+    const float *__restrict__ H, int64_t ld, int64_t P, const double *__restrict__ psi,
+    const Run *__restrict__ runs, int nruns, int64_t k, int64_t t_begin, int64_t t_end,
+    double *__restrict__ partial) {
+    const int nsplit = gridDim.y;
+    const int split = blockIdx.y;
+    const int64_t T = t_end - t_begin;
+    const int64_t ta = t_begin + (T * split) / nsplit;
+    const int64_t tb = t_begin + (T * (split + 1)) / nsplit;
+    const int64_t col = ((int64_t)blockIdx.x * kGemvThreads + threadIdx.x) * 4;
+
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (col < P) {
+        int64_t tr0 = 0;
+        for (int r = 0; r < nruns && tr0 < tb; ++r) {
+            const Run run = runs[r];
+            const int64_t tr1 = tr0 + run.count;
+            const int64_t lo = ta > tr0 ? ta : tr0;
+            const int64_t hi = tb < tr1 ? tb : tr1;
+            if (lo < hi) {
+                const int64_t stride = run.stride;
+                const double coef = (double)run.coef;
+                int64_t m = run.m0 + (lo - tr0) * stride;
+                const float *row = H + (k - m) * ld + col;
+                const int64_t step = stride * ld;
+                int64_t cnt = hi - lo;
+                while (cnt >= kGemvUnroll) {
+                    float4 v[kGemvUnroll];
+                    double w[kGemvUnroll];
+#pragma unroll
+                    for (int u = 0; u < kGemvUnroll; ++u)
+                        v[u] = *reinterpret_cast<const float4 *>(row - u * step);
+#pragma unroll
+                    for (int u = 0; u < kGemvUnroll; ++u) w[u] = coef * psi[m + u * stride];
+#pragma unroll
+                    for (int u = 0; u < kGemvUnroll; ++u) {
+                        a0 = fma(w[u], (double)v[u].x, a0);
+                        a1 = fma(w[u], (double)v[u].y, a1);
+                        a2 = fma(w[u], (double)v[u].z, a2);
+                        a3 = fma(w[u], (double)v[u].w, a3);
+                    }
+                    row -= kGemvUnroll * step;
+                    m += kGemvUnroll * stride;
+                    cnt -= kGemvUnroll;
+                }
+                for (; cnt > 0; --cnt) {
+                    const float4 v = *reinterpret_cast<const float4 *>(row);
+                    const double w = coef * psi[m];
+                    a0 = fma(w, (double)v.x, a0);
+                    a1 = fma(w, (double)v.y, a1);
+                    a2 = fma(w, (double)v.z, a2);
+                    a3 = fma(w, (double)v.w, a3);
+                    row -= step;
+                    m += stride;
+                }
+            }
+            tr0 = tr1;
+        }
+        double *out = partial + (int64_t)split * P + col;
+        out[0] = a0;
+        if (col + 1 < P) out[1] = a1;
+        if (col + 2 < P) out[2] = a2;
+        if (col + 3 < P) out[3] = a3;
+    }
+}
+
+int gemv_splits(int64_t terms, int64_t P) {
+    if (terms <= 0) return 0;
+    const int64_t colblocks = (P + kGemvCols - 1) / kGemvCols;
+    // aim at ~8 workgroups per CU on 256 CUs, at least 16 terms per split
+    int64_t want = (2048 + colblocks - 1) / colblocks;
+    const int64_t by_terms = (terms + 15) / 16;
+    if (want > by_terms) want = by_terms;
+    if (want > kMaxSplits) want = kMaxSplits;
+    if (want < 1) want = 1;
+    return (int)want;
+}
+
+void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, const Run *runs,
+                      int nruns, int64_t k, int64_t t_begin, int64_t t_end, int nsplit,
+                      double *partial, hipStream_t s) {
+    const unsigned colblocks = (unsigned)((P + kGemvCols - 1) / kGemvCols);
+    hipLaunchKernelGGL(hist_gemv_kernel, dim3(colblocks, (unsigned)nsplit), dim3(kGemvThreads), 0,
+                       s, H, ld, P, psi, runs, nruns, k, t_begin, t_end, partial);
+}
+
+__global__ void reduce_partials_kernel(const double *__restrict__ partial, int nsplit, int64_t P,
+                                       const double *__restrict__ base, double *__restrict__ S) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double acc = base ? base[p] : 0.0;
+    for (int q = 0; q < nsplit; ++q) acc += partial[(int64_t)q * P + p];
+    S[p] = acc;
+}
+
+void launch_reduce_partials(const double *partial, int nsplit, int64_t P, const double *base,
+                            double *S, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s,
+                       partial, nsplit, P, base, S);
+}
+
+// ------------------------------------------------------------------ update
+//
+// One step of eq. (21) after the history sum: with S = u[k] + sum of the
+// GEMV partials (the m = 0 term psi(0) u[k] = u[k] is taken from the FP64
+// state), u[k+1] = u[k] + dt f(u[k]) + r Lap(S), Lap the un-normalised 5-point
+// (2D) or 3-point (1D) stencil of eq. (17) with zero values outside the grid.
+// A 2D workgroup updates a 32 x 8 tile; it first forms S on the tile plus a
+// one-point halo in LDS (recomputing the halo from the partials), then applies
+// the stencil from LDS.
+
+constexpr int kTileX = 32;
+constexpr int kTileY = 8;
+
+__device__ __forceinline__ double reaction(int rxn, double rate, double u) {
+    if (rxn == GL_RXN_LINEAR) return -rate * u;
+    if (rxn == GL_RXN_FISHER) return rate * u * (1.0 - u);
+    return 0.0;
+}
+
+__device__ __forceinline__ double sum_at(const double *__restrict__ u,
+                                         const double *__restrict__ partial, int nsplit,
+                                         int64_t P, int64_t p) {
+    double s = u[p];
+    for (int q = 0; q < nsplit; ++q) s += partial[(int64_t)q * P + p];
+    return s;
+}
+
+__global__ __launch_bounds__(kTileX *kTileY) void update2d_kernel(
+    const double *__restrict__ u, double *__restrict__ unew, float *__restrict__ Hnext,
+    const double *__restrict__ partial, int nsplit, int nx, int ny, double r, double dt, int rxn,
+    double rate) {
+    __shared__ double S[kTileY + 2][kTileX + 2];
+    const int64_t P = (int64_t)nx * ny;
+    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
+    for (int i = threadIdx.x; i < (kTileX + 2) * (kTileY + 2); i += kTileX * kTileY) {
+        const int ly = i / (kTileX + 2), lx = i % (kTileX + 2);
+        const int gx = x0 + lx - 1, gy = y0 + ly - 1;
+        double s = 0.0;
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
+            s = sum_at(u, partial, nsplit, P, (int64_t)gy * nx + gx);
+        S[ly][lx] = s;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % kTileX, ly = threadIdx.x / kTileX;
+    const int gx = x0 + lx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) return;
+    const int64_t p = (int64_t)gy * nx + gx;
+    const double lap = S[ly + 1][lx + 2] + S[ly + 1][lx] - 4.0 * S[ly + 1][lx + 1] +
+                       S[ly + 2][lx + 1] + S[ly][lx + 1];
+    const double uk = u[p];
+    const double un = uk + dt * reaction(rxn, rate, uk) + r * lap;
+    unew[p] = un;
+    Hnext[p] = (float)un;
+}
+
+constexpr int kTile1 = 256;
+
+__global__ __launch_bounds__(kTile1) void update1d_kernel(
+    const double *__restrict__ u, double *__restrict__ unew, float *__restrict__ Hnext,
+    const double *__restrict__ partial, int nsplit, int nx, double r, double dt, int rxn,
+    double rate) {
+    __shared__ double S[kTile1 + 2];
+    const int x0 = blockIdx.x * kTile1;
+    for (int i = threadIdx.x; i < kTile1 + 2; i += kTile1) {
+        const int gx = x0 + i - 1;
+        S[i] = (gx >= 0 && gx < nx) ? sum_at(u, partial, nsplit, nx, gx) : 0.0;
+    }
+    __syncthreads();
+    const int gx = x0 + threadIdx.x;
+    if (gx >= nx) return;
+    const int lx = threadIdx.x + 1;
+    const double lap = S[lx + 1] - 2.0 * S[lx] + S[lx - 1];
+    const double uk = u[gx];
+    const double un = uk + dt * reaction(rxn, rate, uk) + r * lap;
+    unew[gx] = un;
+    Hnext[gx] = (float)un;
+}
+
+void launch_update(const Problem &pb, const double *u, double *unew, float *Hnext,
+                   const double *partial, int nsplit, hipStream_t s) {
+    const gl_problem &p = pb.p;
+    if (p.ndim == 1) {
+        hipLaunchKernelGGL(update1d_kernel, dim3((unsigned)((p.nx + kTile1 - 1) / kTile1)),
+                           dim3(kTile1), 0, s, u, unew, Hnext, partial, nsplit, p.nx, pb.r, p.dt,
+                           p.rxn, p.rxn_rate);
+    } else {
+        dim3 grid((unsigned)((p.nx + kTileX - 1) / kTileX), (unsigned)((p.ny + kTileY - 1) / kTileY));
+        hipLaunchKernelGGL(update2d_kernel, grid, dim3(kTileX * kTileY), 0, s, u, unew, Hnext,
+                           partial, nsplit, p.nx, p.ny, pb.r, p.dt, p.rxn, p.rxn_rate);
+    }
+}
+
+// ----------------------------------------------------------------- helpers
+
+__global__ void to_float_kernel(const double *__restrict__ u, float *__restrict__ h, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) h[i] = (float)u[i];
+}
+
+void launch_to_float(const double *u, float *h, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(to_float_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, u, h, n);
+}
+
+__global__ void check_finite_kernel(const double *__restrict__ x, int64_t n, int *flag) {
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        bad |= !isfinite(x[i]);
+    if (bad) atomicOr(flag, 1);
+}
+
+void launch_check_finite(const double *x, int64_t n, int *flag, hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
+}
+
+}  // namespace gl

@@ -1,0 +1,106 @@
+// Per-step memory schedules as run lists (offset m0, count, stride, coef).
+//
+// Full memory (Sec. 2.2, eq. (21)) sums offsets 0..k; short memory (Sec. 3.2,
+// eq. (22)) the window 0..min(L, k), L in steps; adaptive memory (Sec. 3.2,
+// Def. 3.1, Def. 3.2, Prop. 3.1, eq. (24)) the base interval [0, a] and then,
+// interval by interval, one sample per increment of 2i-1 points (its median),
+// weighted by the increment length.  The PARTITION reading tiles each region
+// (a^(i-1), a^i] exactly and takes a short leftover point by point; LITERAL
+// takes the paper's medians a^(i-1) + (2i-1)eta - i + 1 up to a^i, in the
+// interval holding k only whole increments ending by k, then the tail up to
+// k; UNIT_STRIDE is PARTITION with increments of one point.
+#include <algorithm>
+#include <climits>
+
+#include "gl_internal.h"
+
+namespace gl {
+namespace {
+
+// a^e saturated at cap
+int64_t pow_capped(int64_t a, int64_t e, int64_t cap) {
+    int64_t v = 1;
+    for (int64_t i = 0; i < e; ++i) {
+        if (v >= (cap + a - 1) / a) return cap;
+        v *= a;
+    }
+    return std::min(v, cap);
+}
+
+struct Builder {
+    std::vector<Run> *out;
+    int64_t terms = 0;
+    void add(int64_t m0, int64_t count, int64_t stride, int64_t coef) {
+        if (count <= 0) return;
+        out->push_back(Run{(int32_t)m0, (int32_t)count, (int32_t)stride, (int32_t)coef});
+        terms += count;
+    }
+};
+
+void adaptive_partition(Builder &b, int64_t k, int64_t a, bool unit) {
+    b.add(0, std::min(a, k) + 1, 1, 1);
+    int64_t lo = a;
+    for (int64_t i = 2; lo < k; ++i) {
+        const int64_t hi = pow_capped(a, i, k);
+        const int64_t d = unit ? 1 : 2 * i - 1;
+        const int64_t whole = (hi - lo) / d;
+        b.add(lo + 1 + (d - 1) / 2, whole, d, d);        // medians of whole increments
+        b.add(lo + 1 + whole * d, (hi - lo) - whole * d, 1, 1);  // leftover points
+        lo = hi;
+    }
+}
+
+void adaptive_literal(Builder &b, int64_t k, int64_t a) {
+    b.add(0, std::min(a, k) + 1, 1, 1);
+    if (k <= a) return;
+    int64_t reach = a;  // last offset covered by an increment so far
+    for (int64_t i = 2;; ++i) {
+        const int64_t lo = pow_capped(a, i - 1, INT64_MAX / 4);
+        const int64_t hi = pow_capped(a, i, INT64_MAX / 4);
+        const int64_t d = 2 * i - 1;
+        const int64_t first = lo + i;  // first median of interval I_i
+        const bool last = k <= hi;
+        // medians first + e d (e >= 0) up to `limit`
+        const int64_t limit = last ? k - (i - 1) : hi;
+        const int64_t count = limit >= first ? (limit - first) / d + 1 : 0;
+        if (count > 0) {
+            b.add(first, count, d, d);
+            reach = first + (count - 1) * d + (i - 1);
+        }
+        if (last) {
+            b.add(reach + 1, k - reach, 1, 1);
+            return;
+        }
+    }
+}
+
+}  // namespace
+
+Schedule build_schedule(const gl_options &opt, int64_t max_steps) {
+    Schedule s;
+    s.run_begin.reserve(max_steps + 2);
+    s.terms.reserve(max_steps + 1);
+    Builder b{&s.runs};
+    for (int64_t k = 0; k <= max_steps; ++k) {
+        s.run_begin.push_back((int64_t)s.runs.size());
+        b.terms = 0;
+        switch (opt.mem_mode) {
+            case GL_MEM_FULL:
+                b.add(0, k + 1, 1, 1);
+                break;
+            case GL_MEM_SHORT:
+                b.add(0, std::min<int64_t>(opt.short_L, k) + 1, 1, 1);
+                break;
+            default:
+                if (opt.adapt_rule == GL_ADAPT_LITERAL)
+                    adaptive_literal(b, k, opt.adapt_a);
+                else
+                    adaptive_partition(b, k, opt.adapt_a, opt.adapt_rule == GL_ADAPT_UNIT_STRIDE);
+        }
+        s.terms.push_back(b.terms);
+    }
+    s.run_begin.push_back((int64_t)s.runs.size());
+    return s;
+}
+
+}  // namespace gl

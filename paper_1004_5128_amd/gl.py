@@ -1,0 +1,287 @@
+"""Python binding of libgl (include/gl.h): argument marshalling only.
+
+Every entry point of the C ABI is exposed under its own name; all arrays are
+torch CUDA tensors (device memory), passed by pointer, and work runs on the
+caller's current torch stream.  Every step of the solver runs in the HIP
+kernels of libgl.so: if the library is missing this module raises at import
+(there is no fallback).
+
+``Solver`` wraps one context: problems and memory settings are the plain
+dicts of ``paper_1004_5128_amd.workloads``.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgl.so")
+
+GL_OK = 0
+GL_EINVAL = -1
+GL_EUNSTABLE = -2
+GL_ENOMEM = -3
+GL_ECAPACITY = -4
+GL_ESTATE = -5
+GL_ENONFINITE = -6
+GL_EHIP = -7
+GL_EUNSUPPORTED = -8
+
+GL_RXN = {"none": 0, "linear": 1, "fisher": 2}
+GL_MEM = {"full": 0, "short": 1, "adaptive": 2}
+GL_ADAPT = {"partition": 0, "literal": 1, "unit_stride": 2}
+GL_SUM = {"gemv": 0, "toeplitz": 1}
+
+STATUS_NAMES = {0: "GL_OK", -1: "GL_EINVAL", -2: "GL_EUNSTABLE", -3: "GL_ENOMEM",
+                -4: "GL_ECAPACITY", -5: "GL_ESTATE", -6: "GL_ENONFINITE", -7: "GL_EHIP",
+                -8: "GL_EUNSUPPORTED"}
+
+
+class gl_problem(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("rxn", C.c_int32),
+                ("dx", C.c_double), ("dt", C.c_double), ("gamma", C.c_double),
+                ("alpha", C.c_double), ("rxn_rate", C.c_double)]
+
+
+class gl_options(C.Structure):
+    _fields_ = [("mem_mode", C.c_int32), ("adapt_rule", C.c_int32), ("short_L", C.c_int64),
+                ("adapt_a", C.c_int32), ("sum_path", C.c_int32), ("block_B", C.c_int32),
+                ("check_finite", C.c_int32), ("max_steps", C.c_int64),
+                ("ckpt_every", C.c_int64), ("stream", C.c_void_p)]
+
+
+EXPORTS = ["gl_init", "gl_step_n", "gl_adjoint", "gl_free", "gl_last_error", "gl_reset",
+           "gl_set_profiling", "gl_profile", "gl_steps_done", "gl_get_state", "gl_get_weights",
+           "gl_schedule_terms", "gl_history_sum"]
+
+GL_KERNEL_HIST_GEMV = 0
+GL_KERNEL_UPDATE = 1
+GL_KERNEL_TOEPLITZ = 2
+GL_KERNEL_TRIANGLE = 3
+KERNEL_NAMES = {0: "hist_gemv", 1: "update", 2: "toeplitz", 3: "triangle"}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libgl.so is not built (%s); run __graft_entry__.build()" % LIB_PATH)
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    ctxp = C.c_void_p
+    sig = {
+        "gl_init": (i32, [C.POINTER(gl_problem), i32, C.POINTER(gl_options), vp, C.POINTER(ctxp)]),
+        "gl_step_n": (i32, [ctxp, i64, vp]),
+        "gl_adjoint": (i32, [ctxp, vp, vp, vp]),
+        "gl_free": (None, [ctxp]),
+        "gl_last_error": (C.c_char_p, [ctxp]),
+        "gl_reset": (i32, [ctxp, vp]),
+        "gl_set_profiling": (i32, [ctxp, i32]),
+        "gl_profile": (i32, [ctxp, i32, C.POINTER(i64), C.POINTER(C.c_double)]),
+        "gl_steps_done": (i64, [ctxp]),
+        "gl_get_state": (i32, [ctxp, vp]),
+        "gl_get_weights": (i32, [ctxp, i32, i64, vp, vp]),
+        "gl_schedule_terms": (i64, [ctxp, i64]),
+        "gl_history_sum": (i32, [ctxp, i32, i64, vp, i64, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class GLError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), message))
+        self.status = status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _check(status, ctx):
+    if status != GL_OK:
+        raise GLError(status, _lib.gl_last_error(ctx).decode())
+
+
+# ------------------------------------------------------------ raw entry points
+
+def gl_init(problems, nprob, options, u0):
+    """Returns a context handle (c_void_p).  problems: gl_problem array; u0: CUDA float64."""
+    ctx = C.c_void_p()
+    _check(_lib.gl_init(problems, nprob, C.byref(options), _ptr(u0), C.byref(ctx)), None)
+    return ctx
+
+
+def gl_step_n(ctx, n, uT=None):
+    _check(_lib.gl_step_n(ctx, int(n), _ptr(uT)), ctx)
+
+
+def gl_adjoint(ctx, dL_duT, dL_du0, dparams):
+    _check(_lib.gl_adjoint(ctx, _ptr(dL_duT), _ptr(dL_du0), _ptr(dparams)), ctx)
+
+
+def gl_free(ctx):
+    _lib.gl_free(ctx)
+
+
+def gl_last_error(ctx=None):
+    return _lib.gl_last_error(ctx).decode()
+
+
+def gl_reset(ctx, u0):
+    _check(_lib.gl_reset(ctx, _ptr(u0)), ctx)
+
+
+def gl_set_profiling(ctx, on):
+    _check(_lib.gl_set_profiling(ctx, 1 if on else 0), ctx)
+
+
+def gl_profile(ctx, kernel):
+    """(launches, total milliseconds) of a timed kernel since profiling was switched."""
+    n = C.c_int64()
+    ms = C.c_double()
+    _check(_lib.gl_profile(ctx, int(kernel), C.byref(n), C.byref(ms)), ctx)
+    return int(n.value), float(ms.value)
+
+
+def gl_steps_done(ctx):
+    return int(_lib.gl_steps_done(ctx))
+
+
+def gl_get_state(ctx, u):
+    _check(_lib.gl_get_state(ctx, _ptr(u)), ctx)
+
+
+def gl_get_weights(ctx, iprob, count, psi=None, dpsi=None):
+    _check(_lib.gl_get_weights(ctx, int(iprob), int(count), _ptr(psi), _ptr(dpsi)), ctx)
+
+
+def gl_schedule_terms(ctx, k):
+    return int(_lib.gl_schedule_terms(ctx, int(k)))
+
+
+def gl_history_sum(ctx, iprob, k, hist, ld, S):
+    _check(_lib.gl_history_sum(ctx, int(iprob), int(k), _ptr(hist), int(ld), _ptr(S)), ctx)
+
+
+# ---------------------------------------------------------------- convenience
+
+def make_problem(d):
+    return gl_problem(int(d["ndim"]), int(d["nx"]), int(d.get("ny", 1)), GL_RXN[d.get("rxn", "none")],
+                      float(d["dx"]), float(d["dt"]), float(d["gamma"]), float(d["alpha"]),
+                      float(d.get("rate", 0.0)))
+
+
+def make_options(memory, max_steps, sum_path="gemv", block_B=0, check_finite=False,
+                 ckpt_every=0, stream=None):
+    memory = memory or {"mode": "full"}
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    return gl_options(GL_MEM[memory["mode"]], GL_ADAPT[memory.get("rule", "partition")],
+                      int(memory.get("L", 0)), int(memory.get("a", 2)), GL_SUM[sum_path],
+                      int(block_B), 1 if check_finite else 0, int(max_steps), int(ckpt_every),
+                      C.c_void_p(stream))
+
+
+def npoints(d):
+    return int(d["nx"]) * (int(d.get("ny", 1)) if int(d["ndim"]) == 2 else 1)
+
+
+class Solver:
+    """One libgl context for a list of problem dicts sharing a memory setting."""
+
+    def __init__(self, problems, memory, u0, max_steps, sum_path="gemv", block_B=0,
+                 check_finite=False, ckpt_every=0, device="cuda"):
+        if isinstance(problems, dict):
+            problems = [problems]
+        self.problems = list(problems)
+        self.sizes = [npoints(p) for p in self.problems]
+        self.total = sum(self.sizes)
+        arr = (gl_problem * len(self.problems))(*[make_problem(p) for p in self.problems])
+        self._arr = arr
+        self.options = make_options(memory, max_steps, sum_path, block_B, check_finite, ckpt_every)
+        if not torch.is_tensor(u0):
+            u0 = torch.as_tensor(u0)
+        u0 = u0.to(device=device, dtype=torch.float64).contiguous().reshape(-1)
+        if u0.numel() != self.total:
+            raise ValueError("u0 has %d values, problems have %d points" % (u0.numel(), self.total))
+        self.device = u0.device
+        self.ctx = gl_init(arr, len(self.problems), self.options, u0)
+
+    def close(self):
+        if self.ctx is not None:
+            gl_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def k(self):
+        return gl_steps_done(self.ctx)
+
+    def step(self, n, out=None):
+        """Advance n steps; returns the new state (FP64, concatenated)."""
+        if out is None:
+            out = torch.empty(self.total, dtype=torch.float64, device=self.device)
+        gl_step_n(self.ctx, n, out)
+        return out
+
+    def advance(self, n):
+        gl_step_n(self.ctx, n, None)
+
+    def reset(self, u0):
+        u0 = torch.as_tensor(u0).to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
+        gl_reset(self.ctx, u0)
+
+    def set_profiling(self, on):
+        gl_set_profiling(self.ctx, on)
+
+    def profile(self):
+        """{kernel name: (launches, total ms)} since profiling was switched."""
+        return {name: gl_profile(self.ctx, kid) for kid, name in KERNEL_NAMES.items()}
+
+    def state(self):
+        out = torch.empty(self.total, dtype=torch.float64, device=self.device)
+        gl_get_state(self.ctx, out)
+        return out
+
+    def weights(self, iprob=0, count=None):
+        count = self.options.max_steps + 1 if count is None else count
+        psi = torch.empty(count, dtype=torch.float64, device=self.device)
+        dpsi = torch.empty(count, dtype=torch.float64, device=self.device)
+        gl_get_weights(self.ctx, iprob, count, psi, dpsi)
+        return psi, dpsi
+
+    def schedule_terms(self, k):
+        return gl_schedule_terms(self.ctx, k)
+
+    def history_sum(self, k, hist, iprob=0):
+        """S = sum over the step-k schedule of c psi(m) hist[k-m, :P] (hist: [rows, ld] float32)."""
+        P = self.sizes[iprob]
+        S = torch.empty(P, dtype=torch.float64, device=self.device)
+        gl_history_sum(self.ctx, iprob, k, hist, hist.shape[1], S)
+        return S
+
+    def adjoint(self, dL_duT):
+        du0 = torch.empty(self.total, dtype=torch.float64, device=self.device)
+        dpar = torch.empty(len(self.problems) * 3, dtype=torch.float64, device=self.device)
+        gl_adjoint(self.ctx, dL_duT.contiguous(), du0, dpar)
+        return du0, dpar.reshape(len(self.problems), 3)

@@ -1,0 +1,209 @@
+"""Parity of the plain history-sum path (FP32 history, FP64 accumulation, GEMV per
+step) with the FP64 oracle, element by element on the same seeded inputs.
+Tolerance for the whole scheme: relative L2 <= 1e-6."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1004_5128_amd import workloads as W
+from gpu_util import gl, gpu_run, print_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL_PLAIN = 1e-6
+
+
+@pytest.mark.parametrize("gamma", [0.3, 0.5, 0.8, 1.0])
+def test_weights_match_oracle(gamma):
+    print_case("weights", gamma)
+    p = W.problem(1, 8, gamma, 1.0, 0.05)
+    n = 50000
+    with gl().Solver(p, W.memory("full"), np.zeros(8), max_steps=n) as s:
+        psi, dpsi = (t.cpu().numpy() for t in s.weights())
+    ref, dref = oracle.psi(gamma, n), oracle.dpsi(gamma, n)
+    assert np.all(np.abs(psi - ref) <= 1e-12 * np.abs(ref) + 1e-300)
+    assert np.all(np.abs(dpsi - dref) <= 1e-12 * np.abs(dref) + 1e-18)
+
+
+MEMS = [W.memory("full"), W.memory("short", L=0), W.memory("short", L=37),
+        W.memory("adaptive", a=2), W.memory("adaptive", a=4), W.memory("adaptive", a=10),
+        W.memory("adaptive", a=3, rule="literal"), W.memory("adaptive", a=2, rule="literal"),
+        W.memory("adaptive", a=5, rule="unit_stride")]
+MEM_IDS = ["%s-L%d-a%d-%s" % (m["mode"], m["L"], m["a"], m["rule"]) for m in MEMS]
+
+
+@pytest.mark.parametrize("mem", MEMS, ids=MEM_IDS)
+def test_schedule_term_counts_match_oracle(mem):
+    print_case("schedule", mem)
+    p = W.problem(1, 4, 0.7, 1.0, 0.05)
+    n = 3000
+    with gl().Solver(p, mem, np.zeros(4), max_steps=n) as s:
+        for k in list(range(0, 300)) + list(range(300, n + 1, 37)) + [n]:
+            assert s.schedule_terms(k) == len(oracle.schedule(mem, k)[0]), k
+
+
+@pytest.mark.parametrize("mem", MEMS, ids=MEM_IDS)
+@pytest.mark.parametrize("P", [1, 100, 1023, 1025, 5003])
+def test_history_sum_matches_oracle(mem, P):
+    print_case("history_sum", mem, P)
+    gamma = 0.65
+    kmax = 2100
+    rng = np.random.default_rng(P)
+    ld = (P + 3) // 4 * 4
+    H = np.zeros((kmax + 1, ld), np.float32)
+    H[:, :P] = rng.standard_normal((kmax + 1, P)).astype(np.float32)
+    p = W.problem(1, P, gamma, 1.0, 0.05)
+    Hd = torch.as_tensor(H).cuda()
+    with gl().Solver(p, mem, np.zeros(P), max_steps=kmax) as s:
+        for k in (0, 1, 2, 17, 64, 700, kmax):
+            got = s.history_sum(k, Hd).cpu().numpy()
+            ref = oracle.history_sum(gamma, mem, k, H[:, :P])
+            ms, cs = oracle.schedule(mem, k)
+            scale = np.sum(np.abs(cs * oracle.psi(gamma, k)[ms]))
+            assert np.abs(got - ref).max() <= 1e-13 * scale * np.abs(H).max(), (k,)
+
+
+def test_cfg1_full_memory_matches_oracle():
+    w = W.cfg1()
+    print_case(w["name"])
+    got = gpu_run(w["problem"], w["memory"], w["u0"], w["nsteps"])
+    ref = oracle.run(w["problem"], w["memory"], w["u0"], w["nsteps"])
+    assert rel_l2(got, ref) <= TOL_PLAIN
+
+
+@pytest.mark.parametrize("mem", MEMS, ids=MEM_IDS)
+def test_2d_reduced_cfg2_matches_oracle(mem):
+    # the 256^2 / 20000-step workload at 64^2 / 800 steps: same gamma, alpha, reaction, r, u0 recipe
+    w = W.cfg2(n=64, nsteps=800)
+    print_case(w["name"], mem)
+    got = gpu_run(w["problem"], mem, w["u0"], w["nsteps"])
+    ref = oracle.run(w["problem"], mem, w["u0"], w["nsteps"])
+    assert rel_l2(got, ref) <= TOL_PLAIN
+
+
+def test_degenerate_modes_bitwise_equal_full():
+    w = W.cfg2(n=48, nsteps=300)
+    print_case("degenerate", w["name"])
+    p, u0, n = w["problem"], w["u0"], w["nsteps"]
+    full = gpu_run(p, W.memory("full"), u0, n)
+    for mem in (W.memory("short", L=n), W.memory("short", L=10 ** 6), W.memory("adaptive", a=n),
+                W.memory("adaptive", a=2, rule="unit_stride")):
+        assert np.array_equal(gpu_run(p, mem, u0, n), full), mem
+
+
+@pytest.mark.parametrize("shape,rxn", [((37, 23), "fisher"), ((1, 1), "linear"), ((1000,), "none"),
+                                      ((1025, 3), "linear"), ((5, 300), "fisher")])
+def test_ragged_grids_match_oracle(shape, rxn):
+    print_case("ragged", shape, rxn)
+    if len(shape) == 1:
+        p = W.problem(1, shape[0], 0.6, 0.8, 0.15, rxn=rxn, rate=0.7)
+    else:
+        p = W.problem(2, shape[0], 0.6, 0.8, 0.1, rxn=rxn, rate=0.7)
+        p["ny"] = shape[1]
+    u0 = W.uniform_field(p, 9, 0.0, 0.5)
+    mem = W.memory("adaptive", a=3)
+    for m in (W.memory("full"), mem):
+        got = gpu_run(p, m, u0, 400)
+        ref = oracle.run(p, m, u0, 400)
+        assert rel_l2(got, ref) <= TOL_PLAIN
+
+
+def test_ensemble_members_equal_solo_runs():
+    probs = [W.problem(2, 40, 0.4, 1.5, 0.1, rxn="linear", rate=0.3),
+             W.problem(2, 17, 0.9, 0.7, 0.1, rxn="fisher", rate=1.0),
+             W.problem(1, 300, 0.55, 1.0, 0.2)]
+    u0s = [W.gaussian(probs[0], 1), W.uniform_field(probs[1], 2), W.sine_mode(probs[2], 2)]
+    mem = W.memory("adaptive", a=4)
+    n = 250
+    print_case("ensemble", n)
+    G = gl()
+    with G.Solver(probs, mem, torch.as_tensor(np.concatenate(u0s)), max_steps=n) as s:
+        out = s.step(n).cpu().numpy()
+    off = 0
+    for p, u0 in zip(probs, u0s):
+        P = W.npoints(p)
+        assert np.array_equal(out[off:off + P], gpu_run(p, mem, u0, n))
+        assert rel_l2(out[off:off + P], oracle.run(p, mem, u0, n)) <= TOL_PLAIN
+        off += P
+
+
+def test_error_paths():
+    G = gl()
+    p = W.problem(2, 8, 0.7, 1.0, 0.1)
+    u0 = torch.as_tensor(W.gaussian(p, 0)).cuda()
+    print_case("errors")
+    with G.Solver(p, W.memory("full"), u0, max_steps=5) as s:
+        s.step(0)
+        assert s.k == 0
+        s.step(5)
+        with pytest.raises(G.GLError) as e:
+            s.step(1)
+        assert e.value.status == G.GL_ECAPACITY
+        assert s.k == 5
+    bad = u0.clone()
+    bad[3] = float("nan")
+    with pytest.raises(G.GLError) as e:
+        G.Solver(p, W.memory("full"), bad, max_steps=5)
+    assert e.value.status == G.GL_ENONFINITE
+    big = W.problem(2, 512, 0.7, 1.0, 0.1)    # 400000 rows of 1 MB: more than the GPU holds
+    with pytest.raises(G.GLError) as e:
+        G.Solver(big, W.memory("full"), torch.zeros(512 * 512, dtype=torch.float64).cuda(),
+                 max_steps=400000)
+    assert e.value.status == G.GL_ENOMEM
+
+
+def test_check_finite_reports_blow_up():
+    # a state that overflows to Inf through the reaction term is reported, not returned
+    G = gl()
+    p = W.problem(1, 16, 0.9, 1e-6, None, rxn="linear", rate=-1e300, dt=1e-3)
+    u0 = torch.full((16,), 1.0, dtype=torch.float64).cuda()
+    print_case("check_finite")
+    with G.Solver(p, W.memory("full"), u0, max_steps=10, check_finite=True) as s:
+        with pytest.raises(G.GLError) as e:
+            s.step(10)
+        assert e.value.status == G.GL_ENONFINITE
+
+
+def _modal(u, p, modes):
+    x = W.coords(p["nx"])
+    y = W.coords(p["ny"])
+    U = u.reshape(p["ny"], p["nx"])
+    out = []
+    for (a, b) in modes:
+        sx, sy = np.sin(a * np.pi * x), np.sin(b * np.pi * y)
+        out.append(4.0 / ((p["nx"] + 1) * (p["ny"] + 1)) * (sy @ U @ sx))
+    return np.array(out)
+
+
+MODES = [(1, 1), (1, 3), (3, 1), (3, 3), (2, 2), (1, 5), (5, 5), (2, 7)]
+
+
+@pytest.mark.parametrize("mem", [W.memory("full"), W.memory("short", L=1000),
+                                 W.memory("adaptive", a=2), W.memory("adaptive", a=4),
+                                 W.memory("adaptive", a=10)],
+                         ids=["full", "short1000", "adaptive2", "adaptive4", "adaptive10"])
+def test_cfg2_full_size_modal_parity(mem):
+    # The 256^2 / 20000-step workload is linear (f = -0.1 u), so each discrete sine mode of u
+    # evolves on its own by the oracle's scalar recursion: the mode coefficients of the GPU's
+    # u[20000] are sampled outputs the oracle computes one by one.
+    w = W.cfg2()
+    p = w["problem"]
+    print_case(w["name"], mem)
+    got = gpu_run(p, mem, w["u0"], w["nsteps"])
+    c0 = _modal(w["u0"], p, MODES)
+    ref = np.array([c0[i] * oracle.mode_run(p, mem, a, b, 1.0, w["nsteps"])[-1]
+                    for i, (a, b) in enumerate(MODES)])
+    cg = _modal(got, p, MODES)
+    assert np.abs(cg - ref).max() <= TOL_PLAIN * np.abs(ref).max(), (cg, ref)
+
+
+def test_cfg3_full_capacity_prefix_matches_oracle():
+    # 512^2 Fisher-KPP with the full 50000-step history arena (52 GB) allocated; the first
+    # 200 steps against the oracle.
+    w = W.cfg3()
+    n = 200
+    print_case(w["name"], "prefix", n)
+    got = gpu_run(w["problem"], w["memory"], w["u0"], n, max_steps=w["nsteps"])
+    ref = oracle.run(w["problem"], w["memory"], w["u0"], n)
+    assert rel_l2(got, ref) <= TOL_PLAIN
