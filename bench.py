@@ -7,6 +7,11 @@ steps, each summing every stored state), with the inputs resident in device
 memory.  The metric is history MACs/s: one MAC is one (weight x stored state)
 term of a history sum, counted once per grid point.
 
+Two history-sum paths are timed: the plain path (every step reads its
+history rows once, FP32 loads, FP64 accumulation) and the blocked Toeplitz
+path (blocks of B steps take the sum over the states before the block as
+one BF16 hi/lo x 3 matrix product); the headline value is the last path.
+
 Prints one JSON line.  Also reports, for each history-sum path, the relative
 L2 error against the FP64 oracle on an 800-step prefix of the same workload,
 the mode-by-mode error at full length (the workload is linear, so single
@@ -42,15 +47,38 @@ def modal(u, p, modes):
                      (np.sin(b * np.pi * y) @ U @ np.sin(a * np.pi * x)) for a, b in modes])
 
 
-def run_path(path, w, steps, warmup, block_B):
+def copy_calibration(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling the HBM traffic counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: %d x %d bytes read + written" % (reps, nbytes))
+
+
+def run_path(path, w, steps, warmup, block_B, prefix=True):
     import torch
     from paper_1004_5128_amd import gl
     p, n = w["problem"], w["nsteps"]
     P = gl.npoints(p)
     u0 = torch.as_tensor(w["u0"], dtype=torch.float64).cuda()
     s = gl.Solver(p, w["memory"], u0, max_steps=n, sum_path=path, block_B=block_B)
-    macs = P * sum(s.schedule_terms(k) for k in range(n))
-    gemv_bytes = 4 * P * sum(s.schedule_terms(k) - 1 for k in range(n))
+    B = block_B or 256
+    terms = [s.schedule_terms(k) for k in range(n)]
+    macs = P * sum(terms)
+    # algorithmic work of each kernel over one solve (see the design notes):
+    #  hist_gemv: every history row of terms m >= 1 read once, 4 bytes per point
+    #  toeplitz:  6 flops (three BF16 products) per (block row, history row, point)
+    #  triangle:  the in-block rows m = 1..b, 4 bytes per point
+    #  update:    u read, u[k+1] and its FP32 history row written (+ the block sums read)
+    work = {"hist_gemv": ("hbm", 4 * P * sum(t - 1 for t in terms)),
+            "update": ("hbm", (20 + (8 if path == "toeplitz" else 0)) * P * n)}
+    if path == "toeplitz":
+        work["toeplitz"] = ("mfma", 6 * B * P * sum(k0 for k0 in range(B, n, B)))
+        work["triangle"] = ("hbm", 4 * P * sum(k % B for k in range(n)))
+        work["old_reduce"] = ("hbm", 8 * B * P * len(range(B, n, B)))
     for i in range(warmup):
         log(path, "warmup", i)
         s.reset(u0)
@@ -67,14 +95,30 @@ def run_path(path, w, steps, warmup, block_B):
     prof = s.profile()
     s.set_profiling(False)
     uT = s.state().cpu().numpy()
-    # prefix run for the oracle comparison
-    s.reset(u0)
-    s.advance(PREFIX_STEPS)
-    u_prefix = s.state().cpu().numpy()
+    u_prefix = None
+    if prefix:   # prefix run for the oracle comparison
+        s.reset(u0)
+        s.advance(PREFIX_STEPS)
+        u_prefix = s.state().cpu().numpy()
     s.close()
     ms = (t1 - t0) * 1e3 / steps
-    return {"ms_per_step": ms, "macs": macs, "gemv_bytes": gemv_bytes, "prof": prof, "uT": uT,
+    return {"ms_per_step": ms, "macs": macs, "work": work, "prof": prof, "uT": uT,
             "u_prefix": u_prefix, "steps": steps}
+
+
+def roofline_of(kind, work_per_solve, launches_per_solve, ms_per_solve):
+    """Achieved rate of one kernel: algorithmic work per launch / average launch time."""
+    per_launch = work_per_solve / launches_per_solve
+    avg_s = ms_per_solve / launches_per_solve * 1e-3
+    if kind == "mfma":
+        achieved = per_launch / avg_s / 1e12
+        return {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                "algorithmic_flops_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
+    achieved = per_launch / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
 
 
 def main():
@@ -82,9 +126,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--paths", default="gemv")
+    ap.add_argument("--paths", default="gemv,toeplitz",
+                    help="history-sum paths to time; the last one is the headline value")
     ap.add_argument("--block-B", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a 1 GiB device copy (reference for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the solver runs on a single "
@@ -98,8 +145,11 @@ def main():
     p, n = w["problem"], w["nsteps"]
     P = W.npoints(p)
 
+    if args.copy_calibration:
+        copy_calibration()
     paths = [x for x in args.paths.split(",") if x]
-    res = {path: run_path(path, w, args.steps, args.warmup, args.block_B) for path in paths}
+    res = {path: run_path(path, w, args.steps, args.warmup, args.block_B, prefix=not args.no_cpu)
+           for path in paths}
     primary = paths[-1]
 
     out_paths = {}
@@ -124,9 +174,12 @@ def main():
         d = {"ms_per_step": r["ms_per_step"], "value": r["macs"] / (r["ms_per_step"] / 1e3)}
         for name, (cnt, ms) in r["prof"].items():
             if cnt:
-                d.setdefault("kernels", {})[name] = {"launches": cnt // r["steps"],
-                                                     "ms_per_solve": ms / r["steps"],
-                                                     "avg_us": ms * 1e3 / cnt}
+                kd = {"launches": cnt // r["steps"], "ms_per_solve": ms / r["steps"],
+                      "avg_us": ms * 1e3 / cnt}
+                if name in r["work"]:
+                    kind, work = r["work"][name]
+                    kd["roofline"] = roofline_of(kind, work, cnt / r["steps"], ms / r["steps"])
+                d.setdefault("kernels", {})[name] = kd
         if oracle_prefix is not None:
             d["rel_l2_vs_oracle_prefix"] = float(np.linalg.norm(r["u_prefix"] - oracle_prefix) /
                                                  np.linalg.norm(oracle_prefix))
@@ -136,22 +189,21 @@ def main():
         out_paths[path] = d
 
     r = res[primary]
-    prof = r["prof"]
-    roofline = None
-    if primary == "gemv":
-        cnt, ms = prof["hist_gemv"]
-        bytes_per_launch = r["gemv_bytes"] * r["steps"] / cnt
-        achieved = bytes_per_launch / (ms / cnt * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": "hist_gemv_kernel", "achieved": achieved,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": None, "avg_launch_us": ms * 1e3 / cnt,
-                    "algorithmic_bytes_per_launch": bytes_per_launch}
+    # the dominant kernel of the headline path (largest share of the solve's time)
+    kern = out_paths[primary].get("kernels", {})
+    dom = max((k for k in kern if "roofline" in kern[k]), key=lambda k: kern[k]["ms_per_solve"],
+              default=None)
+    roofline = dict(kern[dom]["roofline"], kernel=dom) if dom else None
+    if len(res) > 1 and "gemv" in res and "toeplitz" in res:
+        out_paths["toeplitz_speedup_over_gemv"] = (res["gemv"]["ms_per_step"] /
+                                                   res["toeplitz"]["ms_per_step"])
     value = r["macs"] / (r["ms_per_step"] / 1e3)
     line = {
         "metric": "history MACs/s + rel-L2 vs FP64 oracle; plain FP32 sum vs blocked MFMA sum",
         "value": value, "unit": "history MACs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32 history, f64 accumulate",
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3 mfma (f32 acc) + f64" if primary == "toeplitz" else "f32 history, f64 accumulate",
         "data": "synthetic",
         "config": {"workload": "2d_256x256_gamma0.8_alpha1_linear0.1_gaussian_r0.1_20000steps_full",
                    "grid": [p["nx"], p["ny"]], "time_steps": n, "memory": "full",

@@ -159,11 +159,12 @@ gl_status gl_reset(gl_ctx *ctx, const double *u0);
 /* ---- inspection and component entry points (tests and benchmarks) ---- */
 
 /* Kernels timed by the profiling mode. */
-#define GL_KERNEL_HIST_GEMV 0   /* plain history sum (one launch per step and problem) */
-#define GL_KERNEL_UPDATE 1      /* stencil + reaction update */
-#define GL_KERNEL_TOEPLITZ 2    /* Toeplitz-weight x history product (one launch per block) */
-#define GL_KERNEL_TRIANGLE 3    /* in-block part of the blocked path */
-#define GL_KERNEL_COUNT 4
+#define GL_KERNEL_HIST_GEMV 0    /* plain history sum (one launch per step and problem) */
+#define GL_KERNEL_UPDATE 1       /* stencil + reaction update */
+#define GL_KERNEL_TOEPLITZ 2     /* Toeplitz-weight x history product (one launch per block) */
+#define GL_KERNEL_TRIANGLE 3     /* in-block part of the blocked path's sums */
+#define GL_KERNEL_OLD_REDUCE 4   /* FP64 sum of the Toeplitz product's history chunks */
+#define GL_KERNEL_COUNT 5
 
 /* on != 0: gl_step_n brackets each launch of the timed kernels with HIP
  * events on the context's stream and accumulates their durations; resets

@@ -2,7 +2,9 @@
 // and the step driver that sequences the history-sum and update kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -23,6 +25,11 @@ struct gl_ctx {
     gl::Run *d_runs = nullptr;
     double *partial = nullptr;  // kMaxSplits x max P (FP64)
     int *d_flag = nullptr;
+    float *tpart = nullptr;  // Toeplitz product chunks: max chunks x B x max P (FP32)
+    double *Sblk = nullptr;  // in-block sums, 2 x max P (FP64)
+    int blk_capacity = 0;    // co-resident workgroups of the in-block kernel
+    int B = 256;             // block length of the Toeplitz path
+    gl::Tuning tune;
     std::vector<void *> allocs;
     std::string err;
     // profiling: events bracketing timed kernel launches, resolved at sync points
@@ -101,6 +108,12 @@ gl_status validate(const gl_problem *probs, int32_t nprob, const gl_options *opt
     if (opt->max_steps < 1 || opt->max_steps > (int64_t)INT32_MAX / 2)
         return fail(nullptr, GL_EINVAL, "gl_init: max_steps must be in [1, 2^30]");
     if (opt->ckpt_every < 0) return fail(nullptr, GL_EINVAL, "gl_init: ckpt_every must be >= 0");
+    if (opt->block_B != 0 && opt->block_B != 32 && opt->block_B != 64 && opt->block_B != 128 &&
+        opt->block_B != 256)
+        return fail(nullptr, GL_EINVAL, "gl_init: block_B must be 0, 32, 64, 128 or 256");
+    if (opt->sum_path == GL_SUM_TOEPLITZ_BF16X3 && opt->mem_mode != GL_MEM_FULL)
+        return fail(nullptr, GL_EUNSUPPORTED,
+                    "gl_init: the Toeplitz path sums full memory only (mem_mode must be FULL)");
     for (int32_t i = 0; i < nprob; ++i) {
         const gl_problem &p = probs[i];
         if (p.ndim != 1 && p.ndim != 2)
@@ -131,6 +144,13 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     const gl_options &opt = ctx->opt;
     const int64_t rows = opt.max_steps + 1;
 
+    const bool toep = opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
+    ctx->B = opt.block_B ? opt.block_B : 256;
+    // weights are kept for m up to max_steps + kMaxBlock (the last block's rows reach past k)
+    const int64_t npsi = opt.max_steps + gl::kMaxBlock + 1;
+    const int64_t tab_len = (npsi + gl::kPsiPad + 16 + 7) / 8 * 8;
+    const int nchunk_max = gl::toeplitz_chunks(opt.max_steps, ctx->tune.kchunk);
+
     // capacity: history arena + tables + state
     size_t need = 0;
     int64_t maxP = 0;
@@ -145,10 +165,12 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
         pb.offset = ctx->total_points;
         ctx->total_points += pb.P;
         if (pb.P > maxP) maxP = pb.P;
-        need += (size_t)rows * pb.ld * sizeof(float) + 2 * (size_t)rows * sizeof(double) +
+        need += (size_t)rows * pb.ld * sizeof(float) + 2 * (size_t)npsi * sizeof(double) +
                 2 * (size_t)pb.P * sizeof(double);
+        if (toep) need += 16 * (size_t)tab_len * sizeof(uint16_t) + (size_t)ctx->B * pb.P * sizeof(double);
     }
     need += (size_t)gl::kMaxSplits * maxP * sizeof(double);
+    if (toep) need += ((size_t)nchunk_max * ctx->B * maxP + 4 * (size_t)maxP) * sizeof(float);
     size_t free_b = 0, total_b = 0;
     HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
     if (need + (size_t)(256u << 20) > free_b)
@@ -162,15 +184,29 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
                            ctx->sched.runs.size() * sizeof(gl::Run), hipMemcpyHostToDevice));
     if ((st = dev_alloc(ctx, &ctx->partial, (size_t)gl::kMaxSplits * maxP))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_flag, 1))) return st;
+    if (toep && (st = dev_alloc(ctx, &ctx->tpart, (size_t)std::max(nchunk_max, 1) * ctx->B * maxP)))
+        return st;
+    if (toep && (st = dev_alloc(ctx, &ctx->Sblk, 2 * (size_t)maxP))) return st;
+    if (toep && ctx->tune.persistent) {
+        ctx->blk_capacity = gl::block_steps_capacity();
+        if (ctx->blk_capacity < 1) ctx->tune.persistent = false;
+    }
 
     for (gl::Problem &pb : ctx->probs) {
-        if ((st = dev_alloc(ctx, &pb.psi, rows))) return st;
-        if ((st = dev_alloc(ctx, &pb.dpsi, rows))) return st;
+        if ((st = dev_alloc(ctx, &pb.psi, npsi))) return st;
+        if ((st = dev_alloc(ctx, &pb.dpsi, npsi))) return st;
         if ((st = dev_alloc(ctx, &pb.H, (size_t)rows * pb.ld))) return st;
         if ((st = dev_alloc(ctx, &pb.u[0], pb.P))) return st;
         if ((st = dev_alloc(ctx, &pb.u[1], pb.P))) return st;
-        gl::launch_weights(pb.p.gamma, opt.max_steps, pb.psi, pb.dpsi, ctx->stream);
+        gl::launch_weights(pb.p.gamma, npsi - 1, pb.psi, pb.dpsi, ctx->stream);
         HIP_TRY(ctx, hipGetLastError());
+        if (toep) {
+            pb.tab_len = tab_len;
+            if ((st = dev_alloc(ctx, &pb.psi_tab, 16 * (size_t)tab_len))) return st;
+            if ((st = dev_alloc(ctx, &pb.old, (size_t)ctx->B * pb.P))) return st;
+            gl::launch_psi_tables(pb.psi, npsi, tab_len, pb.psi_tab, ctx->stream);
+            HIP_TRY(ctx, hipGetLastError());
+        }
     }
     return load_initial(ctx, u0);
 }
@@ -236,6 +272,7 @@ gl_status timed(gl_ctx *ctx, int kernel, F &&launch) {
 gl_status load_initial(gl_ctx *ctx, const double *u0) {
     for (gl::Problem &pb : ctx->probs) {
         pb.cur = 0;
+        pb.old_k0 = -1;
         HIP_TRY(ctx, hipMemcpyAsync(pb.u[0], u0 + pb.offset, pb.P * sizeof(double),
                                     hipMemcpyDeviceToDevice, ctx->stream));
         gl::launch_to_float(pb.u[0], pb.H, pb.P, ctx->stream);
@@ -261,23 +298,126 @@ gl_status step_gemv(gl_ctx *ctx) {
         const double *u = pb.u[pb.cur];
         double *un = pb.u[pb.cur ^ 1];
         // term 0 is (m = 0, coef 1): psi(0) u[k] = u[k] comes from the FP64 state
-        const int nsplit = gl::gemv_splits(T - 1, pb.P);
+        const int nsplit = gl::gemv_splits(T - 1, pb.P, ctx->tune.gemv_groups);
+        const bool reverse = ctx->tune.serpentine && (k & 1);
         gl_status st;
         if (nsplit > 0) {
             st = timed(ctx, GL_KERNEL_HIST_GEMV, [&] {
                 gl::launch_hist_gemv(pb.H, pb.ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 1, T,
-                                     nsplit, ctx->partial, ctx->stream);
+                                     nsplit, reverse, ctx->partial, ctx->stream);
             });
             if (st != GL_OK) return st;
         }
         st = timed(ctx, GL_KERNEL_UPDATE, [&] {
-            gl::launch_update(pb, u, un, pb.H + (k + 1) * pb.ld, ctx->partial, nsplit, ctx->stream);
+            gl::launch_update(pb, u, nullptr, un, pb.H + (k + 1) * pb.ld, ctx->partial, nsplit,
+                              ctx->stream);
         });
         if (st != GL_OK) return st;
         pb.cur ^= 1;
     }
     HIP_TRY(ctx, hipGetLastError());
     ctx->k = k + 1;
+    return GL_OK;
+}
+
+// old[b] = sum_{j < k0} psi(k0 + b - j) hist[j] for b < B, on the matrix cores.
+gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int64_t k0,
+                    double *old) {
+    const int nchunk = gl::toeplitz_chunks(k0, ctx->tune.kchunk);
+    gl_status st = timed(ctx, GL_KERNEL_TOEPLITZ, [&] {
+        gl::launch_toeplitz_gemm(ctx->B, hist, ld, pb.P, pb.psi_tab, pb.tab_len, k0,
+                                 ctx->tune.kchunk, ctx->tpart, ctx->stream);
+    });
+    if (st != GL_OK) return st;
+    return timed(ctx, GL_KERNEL_OLD_REDUCE, [&] {
+        gl::launch_old_reduce(ctx->tpart, nchunk, ctx->B, pb.P, old, ctx->stream);
+    });
+}
+
+// One step k -> k + 1 on the blocked path: at the start of each block of B steps the
+// sums over the states before the block are formed by the Toeplitz product; each step
+// adds the states inside the block (terms m = 1..b, plain path) and psi(0) u[k].
+gl_status step_toeplitz(gl_ctx *ctx) {
+    const int64_t k = ctx->k;
+    const int64_t b = k % ctx->B;
+    const int64_t k0 = k - b;
+    const int64_t rb = ctx->sched.run_begin[k];
+    const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
+    for (gl::Problem &pb : ctx->probs) {
+        gl_status st;
+        if (k0 > 0 && pb.old_k0 != k0) {
+            if ((st = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old)) != GL_OK) return st;
+            pb.old_k0 = k0;
+        }
+        const double *u = pb.u[pb.cur];
+        double *un = pb.u[pb.cur ^ 1];
+        const int nsplit = gl::gemv_splits(b, pb.P, ctx->tune.gemv_groups);
+        if (nsplit > 0) {
+            st = timed(ctx, GL_KERNEL_TRIANGLE, [&] {
+                gl::launch_hist_gemv(pb.H, pb.ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 1,
+                                     b + 1, nsplit, false, ctx->partial, ctx->stream);
+            });
+            if (st != GL_OK) return st;
+        }
+        const double *base = k0 > 0 ? pb.old + b * pb.P : nullptr;
+        st = timed(ctx, GL_KERNEL_UPDATE, [&] {
+            gl::launch_update(pb, u, base, un, pb.H + (k + 1) * pb.ld, ctx->partial, nsplit,
+                              ctx->stream);
+        });
+        if (st != GL_OK) return st;
+        pb.cur ^= 1;
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    ctx->k = k + 1;
+    return GL_OK;
+}
+
+// Runs up to n steps on the blocked path with one cooperative launch per block
+// segment: the Toeplitz product at each block start, then the in-block steps.
+gl_status steps_toeplitz_persistent(gl_ctx *ctx, int64_t n) {
+    while (n > 0) {
+        const int64_t k = ctx->k;
+        const int64_t b = k % ctx->B;
+        const int64_t k0 = k - b;
+        const int64_t seg = std::min<int64_t>(n, ctx->B - b);
+        for (gl::Problem &pb : ctx->probs) {
+            gl_status st;
+            if (k0 > 0 && pb.old_k0 != k0) {
+                if ((st = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old)) != GL_OK) return st;
+                pb.old_k0 = k0;
+            }
+            gl::BlockStepArgs args{};
+            args.psi = pb.psi;
+            args.H = pb.H;
+            args.ld = pb.ld;
+            args.P = pb.P;
+            args.ndim = pb.p.ndim;
+            args.nx = pb.p.nx;
+            args.ny = pb.p.ny;
+            args.rxn = pb.p.rxn;
+            args.r = pb.r;
+            args.dt = pb.p.dt;
+            args.rate = pb.p.rxn_rate;
+            args.old = k0 > 0 ? pb.old : nullptr;
+            args.u_cur = pb.u[pb.cur];
+            args.u_next = pb.u[pb.cur ^ 1];
+            args.S = ctx->Sblk;
+            args.k0 = k0;
+            args.b_begin = (int32_t)b;
+            args.b_end = (int32_t)(b + seg);
+            const int groups = gl::block_steps_groups(pb.P, ctx->blk_capacity);
+            hipError_t e = hipSuccess;
+            st = timed(ctx, GL_KERNEL_TRIANGLE,
+                       [&] { e = gl::launch_block_steps(args, groups, ctx->stream); });
+            if (st != GL_OK) return st;
+            if (e != hipSuccess)
+                return fail(ctx, GL_EHIP, "in-block cooperative launch failed: %s",
+                            hipGetErrorString(e));
+            if (seg & 1) pb.cur ^= 1;
+        }
+        ctx->k += seg;
+        n -= seg;
+    }
     return GL_OK;
 }
 
@@ -296,10 +436,13 @@ gl_status gl_init(const gl_problem *probs, int32_t nprob, const gl_options *opt,
                   gl_ctx **out) {
     gl_status st = validate(probs, nprob, opt, u0, out);
     if (st != GL_OK) return st;
-    if (opt->sum_path == GL_SUM_TOEPLITZ_BF16X3)
-        return fail(nullptr, GL_EUNSUPPORTED, "gl_init: the Toeplitz path is not built yet");
     std::unique_ptr<gl_ctx> ctx(new gl_ctx);
     ctx->opt = *opt;
+    if (const char *v = std::getenv("GL_GEMV_GROUPS")) ctx->tune.gemv_groups = std::max(1L, std::atol(v));
+    if (const char *v = std::getenv("GL_GEMV_SERPENTINE")) ctx->tune.serpentine = std::atoi(v) != 0;
+    if (const char *v = std::getenv("GL_BLOCK_PERSISTENT")) ctx->tune.persistent = std::atoi(v) != 0;
+    if (const char *v = std::getenv("GL_TOEPLITZ_KCHUNK"))
+        ctx->tune.kchunk = std::max(64L, std::atol(v) / 64 * 64);
     ctx->stream = static_cast<hipStream_t>(opt->stream);
     st = init_impl(ctx.get(), probs, nprob, u0);
     if (st != GL_OK) {
@@ -319,8 +462,13 @@ gl_status gl_step_n(gl_ctx *ctx, int64_t n, double *uT) {
         return fail(ctx, GL_ECAPACITY, "gl_step_n: %lld + %lld steps exceed max_steps = %lld",
                     (long long)ctx->k, (long long)n, (long long)ctx->opt.max_steps);
     gl_status st;
-    for (int64_t s = 0; s < n; ++s)
-        if ((st = step_gemv(ctx)) != GL_OK) return st;
+    const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
+    if (toep && ctx->tune.persistent) {
+        if ((st = steps_toeplitz_persistent(ctx, n)) != GL_OK) return st;
+    } else {
+        for (int64_t s = 0; s < n; ++s)
+            if ((st = toep ? step_toeplitz(ctx) : step_gemv(ctx)) != GL_OK) return st;
+    }
     if (uT && (st = copy_state(ctx, uT)) != GL_OK) return st;
     if (ctx->opt.check_finite) {
         HIP_TRY(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
@@ -428,11 +576,24 @@ gl_status gl_history_sum(gl_ctx *ctx, int32_t iprob, int64_t k, const float *his
         return fail(ctx, GL_EINVAL, "gl_history_sum: need ld >= P, ld %% 4 == 0, 16-byte aligned");
     const int64_t rb = ctx->sched.run_begin[k];
     const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
-    const int64_t T = ctx->sched.terms[k];
-    const int nsplit = gl::gemv_splits(T, pb.P);
-    gl::launch_hist_gemv(hist, ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 0, T, nsplit,
-                         ctx->partial, ctx->stream);
-    gl::launch_reduce_partials(ctx->partial, nsplit, pb.P, nullptr, S, ctx->stream);
+    int64_t t_end = ctx->sched.terms[k];
+    const double *base = nullptr;
+    if (ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3) {
+        // rows before the block holding k on the matrix cores, rows k0..k on the plain path
+        gl::Problem &pbm = ctx->probs[iprob];
+        const int64_t b = k % ctx->B, k0 = k - b;
+        if (k0 > 0) {
+            pbm.old_k0 = -1;  // old[] is reused as scratch here
+            gl_status st = block_old(ctx, pbm, hist, ld, k0, pbm.old);
+            if (st != GL_OK) return st;
+            base = pbm.old + b * pbm.P;
+        }
+        t_end = b + 1;
+    }
+    const int nsplit = gl::gemv_splits(t_end, pb.P, ctx->tune.gemv_groups);
+    gl::launch_hist_gemv(hist, ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 0, t_end, nsplit,
+                         false, ctx->partial, ctx->stream);
+    gl::launch_reduce_partials(ctx->partial, nsplit, pb.P, base, S, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return GL_OK;

@@ -46,6 +46,11 @@ struct Problem {
     float *H = nullptr;      // [(max_steps + 1) * ld] FP32 history, row j = u[j]
     double *u[2] = {nullptr, nullptr};  // FP64 state, double-buffered
     int cur = 0;             // u[cur] holds the current step
+    // blocked Toeplitz path
+    uint16_t *psi_tab = nullptr;  // BF16 hi/lo weight tables, 2 x 8 shifted copies of tab_len
+    int64_t tab_len = 0;
+    double *old = nullptr;        // [B x P] FP64 sums over the states before the current block
+    int64_t old_k0 = -1;          // block start old[] belongs to (-1: none)
 };
 
 // ---------------------------------------------------------------- kernels
@@ -56,24 +61,77 @@ void launch_weights(double gamma, int64_t n, double *psi, double *dpsi, hipStrea
 // Columns per workgroup of the history GEMV.
 constexpr int kGemvCols = 1024;
 
-// Number of row splits of the history GEMV for `terms` terms over P points.
-int gemv_splits(int64_t terms, int64_t P);
+// Number of row splits of the history GEMV for `terms` terms over P points,
+// aiming at about target_groups workgroups.
+int gemv_splits(int64_t terms, int64_t P, int64_t target_groups);
 constexpr int kMaxSplits = 64;
 
 // partial[s * P + p] = sum over terms t in split s of [t_begin, t_end) of the
-// step-k schedule (runs, nruns) of coef * psi[m] * H[(k - m) * ld + p], FP64.
+// step-k schedule (runs, nruns) of coef * psi[m] * H[(k - m) * ld + p], FP64,
+// accumulated in term order (reverse: from the split's last term down).
 void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, const Run *runs,
                       int nruns, int64_t k, int64_t t_begin, int64_t t_end, int nsplit,
-                      double *partial, hipStream_t s);
+                      bool reverse, double *partial, hipStream_t s);
+
+// Tuning (defaults; GL_GEMV_GROUPS, GL_GEMV_SERPENTINE, GL_TOEPLITZ_KCHUNK and
+// GL_BLOCK_PERSISTENT in the environment override them at gl_init).
+struct Tuning {
+    int64_t gemv_groups = 1024;  // target workgroups per GEMV launch
+    bool serpentine = false;     // alternate the traversal direction every step
+    int64_t kchunk = 2048;       // history rows per Toeplitz product chunk (multiple of 64)
+    bool persistent = true;      // in-block steps as one cooperative launch per block
+};
+
+// ---- blocked Toeplitz path
+constexpr int kPsiPad = 64;   // zero entries before psi(0) in the BF16 weight tables
+constexpr int kMaxBlock = 256;
+
+// BF16 hi/lo weight tables (8 shifted copies each) from the FP64 weights psi[0..npsi).
+void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_t *tab,
+                       hipStream_t s);
+
+// Number of history chunks the product over rows [0, k0) is cut into.
+int toeplitz_chunks(int64_t k0, int64_t kchunk);
+
+// out[c][b][p] (FP32) = sum over rows j in chunk c of [0, k0) of
+// T[b][j] H[j * ld + p] with T[b][j] = psi(k0 + b - j), b < BM, three BF16 products.
+void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
+                          int64_t tab_len, int64_t k0, int64_t kchunk, float *out, hipStream_t s);
+
+// old[b * P + p] = sum_c part[c][b][p] in FP64, chunks in order.
+void launch_old_reduce(const float *part, int nchunk, int64_t BM, int64_t P, double *old,
+                       hipStream_t s);
+
+// Arguments of the persistent in-block kernel: steps k0 + b for b in [b_begin, b_end)
+// of one problem, u_cur holding u[k0 + b_begin].
+struct BlockStepArgs {
+    const double *psi;
+    float *H;
+    int64_t ld, P;
+    int32_t ndim, nx, ny, rxn;
+    double r, dt, rate;
+    const double *old;  // [B x P] sums over the states before the block, or nullptr (k0 = 0)
+    double *u_cur, *u_next;
+    double *S;          // [2 x P] scratch, double-buffered by step parity
+    int64_t k0;
+    int32_t b_begin, b_end;
+};
+
+// Maximum co-resident workgroups of the in-block kernel on the current device.
+int block_steps_capacity();
+// Workgroups used for P points (<= capacity).
+int block_steps_groups(int64_t P, int capacity);
+// One cooperative launch running the steps of `args`.
+hipError_t launch_block_steps(const BlockStepArgs &args, int groups, hipStream_t s);
 
 // S[p] = sum_s partial[s * P + p] (+ base[p] if base != nullptr), fixed order.
 void launch_reduce_partials(const double *partial, int nsplit, int64_t P, const double *base,
                             double *S, hipStream_t s);
 
-// One explicit step: S = u + sum_s partial[s]; unew = u + dt f(u) + r Lap(S);
-// Hnext = (float) unew.
-void launch_update(const Problem &pb, const double *u, double *unew, float *Hnext,
-                   const double *partial, int nsplit, hipStream_t s);
+// One explicit step: S = u (+ base) + sum_s partial[s]; unew = u + dt f(u) + r Lap(S);
+// Hnext = (float) unew.  base (nullable) holds the sum over states before the block.
+void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
+                   float *Hnext, const double *partial, int nsplit, hipStream_t s);
 
 // h[p] = (float) u[p]
 void launch_to_float(const double *u, float *h, int64_t n, hipStream_t s);

@@ -52,7 +52,7 @@ constexpr int kGemvUnroll = 8;
 __global__ __launch_bounds__(kGemvThreads) void hist_gemv_kernel(
     const float *__restrict__ H, int64_t ld, int64_t P, const double *__restrict__ psi,
     const Run *__restrict__ runs, int nruns, int64_t k, int64_t t_begin, int64_t t_end,
-    double *__restrict__ partial) {
+    int reverse, double *__restrict__ partial) {
     const int nsplit = gridDim.y;
     const int split = blockIdx.y;
     const int64_t T = t_end - t_begin;
@@ -62,16 +62,31 @@ __global__ __launch_bounds__(kGemvThreads) void hist_gemv_kernel(
 
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (col < P) {
+        // Runs are visited in order; with `reverse` each split walks its terms from the
+        // last to the first (oldest row first), so that consecutive steps traverse the
+        // history in opposite directions and the rows one step read last are still in
+        // the last-level cache when the next step starts.
         int64_t tr0 = 0;
-        for (int r = 0; r < nruns && tr0 < tb; ++r) {
+        if (reverse)
+            for (int r = 0; r < nruns; ++r) tr0 += runs[r].count;
+        for (int rr = 0; rr < nruns; ++rr) {
+            const int r = reverse ? nruns - 1 - rr : rr;
             const Run run = runs[r];
-            const int64_t tr1 = tr0 + run.count;
+            int64_t tr1;
+            if (reverse) {
+                tr1 = tr0;
+                tr0 = tr1 - run.count;
+                if (tr1 <= ta) break;
+            } else {
+                tr1 = tr0 + run.count;
+                if (tr0 >= tb) break;
+            }
             const int64_t lo = ta > tr0 ? ta : tr0;
             const int64_t hi = tb < tr1 ? tb : tr1;
             if (lo < hi) {
-                const int64_t stride = run.stride;
+                const int64_t stride = reverse ? -(int64_t)run.stride : (int64_t)run.stride;
                 const double coef = (double)run.coef;
-                int64_t m = run.m0 + (lo - tr0) * stride;
+                int64_t m = run.m0 + ((reverse ? hi - 1 : lo) - tr0) * (int64_t)run.stride;
                 const float *row = H + (k - m) * ld + col;
                 const int64_t step = stride * ld;
                 int64_t cnt = hi - lo;
@@ -105,7 +120,7 @@ __global__ __launch_bounds__(kGemvThreads) void hist_gemv_kernel(
                     m += stride;
                 }
             }
-            tr0 = tr1;
+            if (!reverse) tr0 = tr1;
         }
         double *out = partial + (int64_t)split * P + col;
         out[0] = a0;
@@ -115,11 +130,11 @@ __global__ __launch_bounds__(kGemvThreads) void hist_gemv_kernel(
     }
 }
 
-int gemv_splits(int64_t terms, int64_t P) {
+int gemv_splits(int64_t terms, int64_t P, int64_t target_groups) {
     if (terms <= 0) return 0;
     const int64_t colblocks = (P + kGemvCols - 1) / kGemvCols;
-    // aim at ~8 workgroups per CU on 256 CUs, at least 16 terms per split
-    int64_t want = (2048 + colblocks - 1) / colblocks;
+    // aim at target_groups workgroups (default ~8 per CU on 256 CUs), >= 16 terms per split
+    int64_t want = (target_groups + colblocks - 1) / colblocks;
     const int64_t by_terms = (terms + 15) / 16;
     if (want > by_terms) want = by_terms;
     if (want > kMaxSplits) want = kMaxSplits;
@@ -129,10 +144,10 @@ int gemv_splits(int64_t terms, int64_t P) {
 
 void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, const Run *runs,
                       int nruns, int64_t k, int64_t t_begin, int64_t t_end, int nsplit,
-                      double *partial, hipStream_t s) {
+                      bool reverse, double *partial, hipStream_t s) {
     const unsigned colblocks = (unsigned)((P + kGemvCols - 1) / kGemvCols);
     hipLaunchKernelGGL(hist_gemv_kernel, dim3(colblocks, (unsigned)nsplit), dim3(kGemvThreads), 0,
-                       s, H, ld, P, psi, runs, nruns, k, t_begin, t_end, partial);
+                       s, H, ld, P, psi, runs, nruns, k, t_begin, t_end, reverse ? 1 : 0, partial);
 }
 
 __global__ void reduce_partials_kernel(const double *__restrict__ partial, int nsplit, int64_t P,
@@ -170,15 +185,27 @@ __device__ __forceinline__ double reaction(int rxn, double rate, double u) {
 }
 
 __device__ __forceinline__ double sum_at(const double *__restrict__ u,
+                                         const double *__restrict__ base,
                                          const double *__restrict__ partial, int nsplit,
                                          int64_t P, int64_t p) {
+    // loads issued eight at a time, added in split order (fixed rounding)
     double s = u[p];
-    for (int q = 0; q < nsplit; ++q) s += partial[(int64_t)q * P + p];
+    if (base) s += base[p];
+    int q = 0;
+    for (; q + 8 <= nsplit; q += 8) {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = partial[(int64_t)(q + i) * P + p];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += v[i];
+    }
+    for (; q < nsplit; ++q) s += partial[(int64_t)q * P + p];
     return s;
 }
 
 __global__ __launch_bounds__(kTileX *kTileY) void update2d_kernel(
-    const double *__restrict__ u, double *__restrict__ unew, float *__restrict__ Hnext,
+    const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
+    float *__restrict__ Hnext,
     const double *__restrict__ partial, int nsplit, int nx, int ny, double r, double dt, int rxn,
     double rate) {
     __shared__ double S[kTileY + 2][kTileX + 2];
@@ -189,7 +216,7 @@ __global__ __launch_bounds__(kTileX *kTileY) void update2d_kernel(
         const int gx = x0 + lx - 1, gy = y0 + ly - 1;
         double s = 0.0;
         if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-            s = sum_at(u, partial, nsplit, P, (int64_t)gy * nx + gx);
+            s = sum_at(u, base, partial, nsplit, P, (int64_t)gy * nx + gx);
         S[ly][lx] = s;
     }
     __syncthreads();
@@ -208,14 +235,15 @@ __global__ __launch_bounds__(kTileX *kTileY) void update2d_kernel(
 constexpr int kTile1 = 256;
 
 __global__ __launch_bounds__(kTile1) void update1d_kernel(
-    const double *__restrict__ u, double *__restrict__ unew, float *__restrict__ Hnext,
+    const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
+    float *__restrict__ Hnext,
     const double *__restrict__ partial, int nsplit, int nx, double r, double dt, int rxn,
     double rate) {
     __shared__ double S[kTile1 + 2];
     const int x0 = blockIdx.x * kTile1;
     for (int i = threadIdx.x; i < kTile1 + 2; i += kTile1) {
         const int gx = x0 + i - 1;
-        S[i] = (gx >= 0 && gx < nx) ? sum_at(u, partial, nsplit, nx, gx) : 0.0;
+        S[i] = (gx >= 0 && gx < nx) ? sum_at(u, base, partial, nsplit, nx, gx) : 0.0;
     }
     __syncthreads();
     const int gx = x0 + threadIdx.x;
@@ -228,17 +256,17 @@ __global__ __launch_bounds__(kTile1) void update1d_kernel(
     Hnext[gx] = (float)un;
 }
 
-void launch_update(const Problem &pb, const double *u, double *unew, float *Hnext,
-                   const double *partial, int nsplit, hipStream_t s) {
+void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
+                   float *Hnext, const double *partial, int nsplit, hipStream_t s) {
     const gl_problem &p = pb.p;
     if (p.ndim == 1) {
         hipLaunchKernelGGL(update1d_kernel, dim3((unsigned)((p.nx + kTile1 - 1) / kTile1)),
-                           dim3(kTile1), 0, s, u, unew, Hnext, partial, nsplit, p.nx, pb.r, p.dt,
-                           p.rxn, p.rxn_rate);
+                           dim3(kTile1), 0, s, u, base, unew, Hnext, partial, nsplit, p.nx, pb.r,
+                           p.dt, p.rxn, p.rxn_rate);
     } else {
         dim3 grid((unsigned)((p.nx + kTileX - 1) / kTileX), (unsigned)((p.ny + kTileY - 1) / kTileY));
-        hipLaunchKernelGGL(update2d_kernel, grid, dim3(kTileX * kTileY), 0, s, u, unew, Hnext,
-                           partial, nsplit, p.nx, p.ny, pb.r, p.dt, p.rxn, p.rxn_rate);
+        hipLaunchKernelGGL(update2d_kernel, grid, dim3(kTileX * kTileY), 0, s, u, base, unew,
+                           Hnext, partial, nsplit, p.nx, p.ny, pb.r, p.dt, p.rxn, p.rxn_rate);
     }
 }
 

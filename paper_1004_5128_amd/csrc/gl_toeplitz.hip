@@ -1,0 +1,238 @@
+// Blocked Toeplitz history sum on gfx950 BF16 matrix cores.
+//
+// With full memory (Sec. 2.2, eq. (21)) step k sums psi(gamma, k - j) u[j] over
+// every stored state j <= k.  For a block of B consecutive steps k = k0 + b
+// (b = 0..B-1) the part over the states before the block,
+//
+//     Old[b, p] = sum_{j < k0} psi(gamma, k0 + b - j) H[j, p],
+//
+// is a matrix product T H with the Toeplitz weight matrix T[b, j] =
+// psi(k0 + b - j) (B x k0) and the FP32 history H (k0 x P).  It is computed once
+// per block on the matrix cores with each operand split into two BF16 parts,
+// x = hi + lo (hi = x rounded to BF16, lo = the remainder rounded to BF16), and
+// three products hi.hi + hi.lo + lo.hi accumulated in FP32; the history rows are
+// split on the fly, the weights come from precomputed split tables.  The
+// history dimension is cut into chunks whose FP32 partial products are summed in
+// FP64, in chunk order, by a second kernel.  The rest of each step's sum (the
+// states inside the block) is summed by the plain path.
+#include <hip/hip_runtime.h>
+
+#include "gl_internal.h"
+
+namespace gl {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// BF16 bits of f rounded to nearest even (finite inputs).
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+// ------------------------------------------------------------ weight tables
+//
+// tab[h][s][i] (h = 0 hi, 1 lo; s = 0..7) holds part h of psi(i - kPsiPad + s),
+// zero outside 0..npsi-1.  Eight shifted copies let a lane fetch any eight
+// consecutive weights psi(m .. m+7) with one aligned 16-byte load (copy
+// s = (m + kPsiPad) mod 8 at index m + kPsiPad - s).
+__global__ void psi_tables_kernel(const double *__restrict__ psi, int64_t npsi, int64_t tab_len,
+                                  uint16_t *__restrict__ tab) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int s = blockIdx.y;
+    if (i >= tab_len) return;
+    const int64_t m = i - kPsiPad + s;
+    const double v = (m >= 0 && m < npsi) ? psi[m] : 0.0;
+    const uint32_t hb = bf16_bits((float)v);
+    const double hv = (double)__uint_as_float(hb << 16);
+    const uint32_t lb = bf16_bits((float)(v - hv));
+    tab[(int64_t)s * tab_len + i] = (uint16_t)hb;
+    tab[(int64_t)(8 + s) * tab_len + i] = (uint16_t)lb;
+}
+
+void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_t *tab,
+                       hipStream_t s) {
+    dim3 grid((unsigned)((tab_len + 255) / 256), 8);
+    hipLaunchKernelGGL(psi_tables_kernel, grid, dim3(256), 0, s, psi, npsi, tab_len, tab);
+}
+
+// --------------------------------------------------------------- the GEMM
+//
+// Workgroup tile: all BM rows of the block x kTN points, 4 waves; K steps of
+// kTK history rows staged through LDS.  Each lane loads 8 rows x 4 points of
+// FP32 history (16-byte loads), splits them into BF16 hi/lo and stores them
+// transposed, [point][row], so that an MFMA B operand (8 consecutive rows of
+// one point) is one 16-byte LDS read.  Inside each group of 8 rows the order is
+// reversed, which makes the matching A operand (the weights of those rows for
+// one output row b) eight consecutive ascending psi values.  The next K step's
+// history loads are issued before the current step's MFMAs.
+//
+// v_mfma_f32_32x32x16_bf16 lane layout (wave64): A lane l holds row l%32,
+// k = 8(l/32)..+7; B lane l holds column l%32, the same k; the accumulator
+// lane l holds column l%32, rows 8(r/4) + 4(l/32) + r%4 for r = 0..15.
+
+constexpr int kTN = 128;              // points per workgroup
+constexpr int kTK = 64;               // history rows per K step
+constexpr int kLdsRow = kTK / 8 + 1;  // 16-byte words per point in LDS (one pad word)
+
+template <int BM>
+__global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
+    const float *__restrict__ H, int64_t ld, int64_t P, const u32x4_t *__restrict__ tab,
+    int64_t tab_len, int64_t k0, int64_t kchunk, float *__restrict__ out) {
+    constexpr int WM = BM >= 128 ? 4 : BM / 32;  // waves along the block rows
+    constexpr int WN = 4 / WM;                   // waves along the points
+    constexpr int RB = BM / 32 / WM;             // 32-row blocks per wave
+    constexpr int CB = kTN / 32 / WN;            // 32-point blocks per wave
+    __shared__ u32x4_t lhi[kTN * kLdsRow];
+    __shared__ u32x4_t llo[kTN * kLdsRow];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wm = wave % WM, wn = wave / WM;
+    const int g = lane >> 5;   // which 8-row half of a 16-row MFMA step this lane feeds
+    const int64_t n0 = (int64_t)blockIdx.x * kTN;
+    const int64_t j_begin = (int64_t)blockIdx.y * kchunk;
+    const int64_t j_end = j_begin + kchunk < k0 ? j_begin + kchunk : k0;
+    const int64_t tab_words = tab_len / 8;  // 16-byte words per table
+
+    // loader: 32 groups of 4 points x 8 groups of 8 rows
+    const int ng = tid & 31, kg = tid >> 5;
+    const int64_t col = n0 + ng * 4;
+    const bool col_ok = col < P;  // P <= ld, ld % 4 == 0: the 16-byte load stays in the row
+
+    f32x16_t acc[RB][CB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) acc[i][j] = f32x16_t{};
+
+    float4 pre[8];
+    auto load_tile = [&](int64_t jt) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t row = jt + kg * 8 + e;
+            pre[e] = (col_ok && row < j_end) ? *reinterpret_cast<const float4 *>(H + row * ld + col)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto stage_tile = [&]() {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            uint32_t hb[8], lb[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = c == 0 ? pre[e].x : c == 1 ? pre[e].y : c == 2 ? pre[e].z : pre[e].w;
+                hb[e] = bf16_bits(v);
+                lb[e] = bf16_bits(v - __uint_as_float(hb[e] << 16));
+            }
+            // element p of the group holds row 7 - p
+            const u32x4_t h4 = {hb[7] | (hb[6] << 16), hb[5] | (hb[4] << 16), hb[3] | (hb[2] << 16),
+                                hb[1] | (hb[0] << 16)};
+            const u32x4_t l4 = {lb[7] | (lb[6] << 16), lb[5] | (lb[4] << 16), lb[3] | (lb[2] << 16),
+                                lb[1] | (lb[0] << 16)};
+            lhi[(ng * 4 + c) * kLdsRow + kg] = h4;
+            llo[(ng * 4 + c) * kLdsRow + kg] = l4;
+        }
+    };
+
+    if (j_begin < j_end) load_tile(j_begin);
+    for (int64_t jt = j_begin; jt < j_end; jt += kTK) {
+        __syncthreads();  // the previous step's MFMAs are done with LDS
+        stage_tile();
+        __syncthreads();
+        if (jt + kTK < j_end) load_tile(jt + kTK);
+#pragma unroll
+        for (int q = 0; q < kTK / 16; ++q) {
+            u32x4_t bh[CB], bl[CB];
+#pragma unroll
+            for (int j = 0; j < CB; ++j) {
+                const int n = (wn * CB + j) * 32 + (lane & 31);
+                bh[j] = lhi[n * kLdsRow + 2 * q + g];
+                bl[j] = llo[n * kLdsRow + 2 * q + g];
+            }
+#pragma unroll
+            for (int i = 0; i < RB; ++i) {
+                const int b = (wm * RB + i) * 32 + (lane & 31);
+                // weights of rows jt+16q+8g+7-p, p = 0..7: psi(mstart + p)
+                const int64_t idx = k0 + b - jt - 16 * q - 8 * g - 7 + kPsiPad;
+                const int s = (int)(idx & 7);
+                const int64_t w = (idx - s) >> 3;
+                const u32x4_t ah = tab[(int64_t)s * tab_words + w];
+                const u32x4_t al = tab[(int64_t)(8 + s) * tab_words + w];
+                const bf16x8_t Ah = __builtin_bit_cast(bf16x8_t, ah);
+                const bf16x8_t Al = __builtin_bit_cast(bf16x8_t, al);
+#pragma unroll
+                for (int j = 0; j < CB; ++j) {
+                    const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, bh[j]);
+                    const bf16x8_t Bl = __builtin_bit_cast(bf16x8_t, bl[j]);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    }
+
+    float *dst = out + (int64_t)blockIdx.y * BM * P;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            const int64_t n = n0 + (wn * CB + j) * 32 + (lane & 31);
+            if (n < P) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int b = (wm * RB + i) * 32 + 8 * (r / 4) + 4 * g + (r % 4);
+                    dst[(int64_t)b * P + n] = acc[i][j][r];
+                }
+            }
+        }
+}
+
+int toeplitz_chunks(int64_t k0, int64_t kchunk) {
+    return k0 <= 0 ? 0 : (int)((k0 + kchunk - 1) / kchunk);
+}
+
+void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
+                          int64_t tab_len, int64_t k0, int64_t kchunk, float *out, hipStream_t s) {
+    const int nchunk = toeplitz_chunks(k0, kchunk);
+    if (nchunk == 0) return;
+    dim3 grid((unsigned)((P + kTN - 1) / kTN), (unsigned)nchunk);
+    const u32x4_t *t = reinterpret_cast<const u32x4_t *>(tab);
+    switch (BM) {
+        case 32:
+            hipLaunchKernelGGL(toeplitz_gemm_kernel<32>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            break;
+        case 64:
+            hipLaunchKernelGGL(toeplitz_gemm_kernel<64>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            break;
+        case 128:
+            hipLaunchKernelGGL(toeplitz_gemm_kernel<128>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            break;
+        default:
+            hipLaunchKernelGGL(toeplitz_gemm_kernel<256>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            break;
+    }
+}
+
+// Old[b * P + p] = sum over chunks c (in order) of part[(c * BM + b) * P + p], FP64.
+__global__ void old_reduce_kernel(const float *__restrict__ part, int nchunk, int64_t BP,
+                                  double *__restrict__ old) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= BP) return;
+    double s = 0.0;
+    for (int c = 0; c < nchunk; ++c) s += (double)part[(int64_t)c * BP + i];
+    old[i] = s;
+}
+
+void launch_old_reduce(const float *part, int nchunk, int64_t BM, int64_t P, double *old,
+                       hipStream_t s) {
+    const int64_t BP = BM * P;
+    hipLaunchKernelGGL(old_reduce_kernel, dim3((unsigned)((BP + 255) / 256)), dim3(256), 0, s, part,
+                       nchunk, BP, old);
+}
+
+}  // namespace gl

@@ -58,7 +58,8 @@ GL_KERNEL_HIST_GEMV = 0
 GL_KERNEL_UPDATE = 1
 GL_KERNEL_TOEPLITZ = 2
 GL_KERNEL_TRIANGLE = 3
-KERNEL_NAMES = {0: "hist_gemv", 1: "update", 2: "toeplitz", 3: "triangle"}
+GL_KERNEL_OLD_REDUCE = 4
+KERNEL_NAMES = {0: "hist_gemv", 1: "update", 2: "toeplitz", 3: "triangle", 4: "old_reduce"}
 
 
 def _load():

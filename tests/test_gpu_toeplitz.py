@@ -1,0 +1,175 @@
+"""Parity of the blocked Toeplitz path (history before each block of B steps summed as
+one BF16 hi/lo x 3 matrix product with FP32 accumulation, FP64 chunk sums; the rest on
+the plain path) with the FP64 oracle.  Tolerance: relative L2 <= 1e-5."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1004_5128_amd import workloads as W
+from gpu_util import gl, gpu_run, print_case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL_MFMA = 1e-5
+
+
+@pytest.fixture(params=["persistent", "per_step"])
+def block_mode(request):
+    """In-block steps as one cooperative launch per block, or two launches per step."""
+    old = os.environ.get("GL_BLOCK_PERSISTENT")
+    os.environ["GL_BLOCK_PERSISTENT"] = "1" if request.param == "persistent" else "0"
+    yield request.param
+    if old is None:
+        del os.environ["GL_BLOCK_PERSISTENT"]
+    else:
+        os.environ["GL_BLOCK_PERSISTENT"] = old
+
+
+@pytest.mark.parametrize("B", [32, 64, 128, 256])
+@pytest.mark.parametrize("P", [1, 129, 1000, 4097])
+def test_block_history_sum_matches_oracle(B, P):
+    # One history sum at several positions relative to the block boundaries, over a seeded
+    # FP32 history, against FP64 dot products of the same rows.
+    print_case("toeplitz history_sum", B, P)
+    gamma = 0.6
+    kmax = 3000
+    rng = np.random.default_rng(1000 + P)
+    ld = (P + 3) // 4 * 4
+    H = np.zeros((kmax + 1, ld), np.float32)
+    H[:, :P] = rng.uniform(-1.0, 1.0, (kmax + 1, P)).astype(np.float32)
+    Hd = torch.as_tensor(H).cuda()
+    p = W.problem(1, P, gamma, 1.0, 0.05)
+    mem = W.memory("full")
+    psi = oracle.psi(gamma, kmax)
+    with gl().Solver(p, mem, np.zeros(P), max_steps=kmax, sum_path="toeplitz", block_B=B) as s:
+        for k in (0, 5, B - 1, B, B + 1, 2 * B + 7, 1000, 2047, 2048, 2049, kmax):
+            if k > kmax:
+                continue
+            got = s.history_sum(k, Hd).cpu().numpy()
+            ref = oracle.history_sum(gamma, mem, k, H[:, :P])
+            scale = np.sum(np.abs(psi[:k + 1]))   # sum |psi(m) H[k-m]| <= scale * max|H|
+            assert np.abs(got - ref).max() <= TOL_MFMA * scale, (k, np.abs(got - ref).max())
+
+
+def test_block_history_sum_full_depth():
+    # At the depth of the 512^2 / 50000-step workload: 4096 sampled columns, 50001 rows.
+    gamma = 0.6
+    kmax = 50000
+    P = 4096
+    print_case("toeplitz full depth", kmax, P)
+    rng = np.random.default_rng(3)
+    H = rng.uniform(0.0, 0.1, (kmax + 1, P)).astype(np.float32)
+    Hd = torch.as_tensor(H).cuda()
+    p = W.problem(1, P, gamma, 0.5, 0.05)
+    mem = W.memory("full")
+    psi = oracle.psi(gamma, kmax)
+    with gl().Solver(p, mem, np.zeros(P), max_steps=kmax, sum_path="toeplitz") as s:
+        for k in (kmax - 300, kmax):
+            got = s.history_sum(k, Hd).cpu().numpy()
+            ref = oracle.history_sum(gamma, mem, k, H)
+            scale = 0.1 * np.sum(np.abs(psi[:k + 1]))
+            assert np.abs(got - ref).max() <= TOL_MFMA * scale
+
+
+def test_cfg1_toeplitz_matches_oracle(block_mode):
+    w = W.cfg1()
+    print_case(w["name"], "toeplitz", block_mode)
+    got = gpu_run(w["problem"], w["memory"], w["u0"], w["nsteps"], sum_path="toeplitz")
+    ref = oracle.run(w["problem"], w["memory"], w["u0"], w["nsteps"])
+    assert rel_l2(got, ref) <= TOL_MFMA
+
+
+@pytest.mark.parametrize("B", [32, 64, 128, 256])
+def test_2d_reduced_cfg2_toeplitz_matches_oracle(B, block_mode):
+    w = W.cfg2(n=64, nsteps=1100)
+    print_case(w["name"], "toeplitz", B, block_mode)
+    got = gpu_run(w["problem"], w["memory"], w["u0"], w["nsteps"], sum_path="toeplitz", block_B=B)
+    ref = oracle.run(w["problem"], w["memory"], w["u0"], w["nsteps"])
+    assert rel_l2(got, ref) <= TOL_MFMA
+
+
+@pytest.mark.parametrize("shape", [(48, 48), (37, 23), (1, 1), (130, 3)])
+def test_fisher_ragged_toeplitz_matches_oracle(shape, block_mode):
+    p = W.problem(2, shape[0], 0.6, 0.5, 0.1, rxn="fisher", rate=1.0)
+    p["ny"] = shape[1]
+    u0 = W.uniform_field(p, 3)
+    n = 700
+    print_case("fisher toeplitz", shape, block_mode)
+    got = gpu_run(p, W.memory("full"), u0, n, sum_path="toeplitz", block_B=64)
+    ref = oracle.run(p, W.memory("full"), u0, n)
+    assert rel_l2(got, ref) <= TOL_MFMA
+
+
+def test_split_calls_equal_one_call(block_mode):
+    # stopping inside a block and continuing gives the same bits as one call
+    w = W.cfg2(n=40, nsteps=600)
+    print_case("toeplitz split calls", block_mode)
+    G = gl()
+    u0 = torch.as_tensor(w["u0"])
+    with G.Solver(w["problem"], w["memory"], u0, max_steps=600, sum_path="toeplitz",
+                  block_B=128) as s:
+        one = s.step(600).cpu().numpy()
+        s.reset(u0)
+        s.step(100)
+        s.step(157)
+        two = s.step(343).cpu().numpy()
+    assert np.array_equal(one, two)
+
+
+def test_toeplitz_needs_full_memory():
+    G = gl()
+    p = W.problem(2, 8, 0.7, 1.0, 0.1)
+    with pytest.raises(G.GLError) as e:
+        G.Solver(p, W.memory("adaptive", a=2), np.zeros(64), max_steps=10, sum_path="toeplitz")
+    assert e.value.status == G.GL_EUNSUPPORTED
+
+
+def test_persistent_and_per_step_agree():
+    # the two in-block schedules differ only in summation order
+    w = W.cfg2(n=96, nsteps=900)
+    outs = []
+    for mode in ("1", "0"):
+        os.environ["GL_BLOCK_PERSISTENT"] = mode
+        try:
+            print_case("persistent", mode)
+            outs.append(gpu_run(w["problem"], w["memory"], w["u0"], w["nsteps"],
+                                sum_path="toeplitz", block_B=128))
+        finally:
+            del os.environ["GL_BLOCK_PERSISTENT"]
+    assert rel_l2(outs[0], outs[1]) <= 1e-12
+
+
+def _modal(u, p, modes):
+    x, y = W.coords(p["nx"]), W.coords(p["ny"])
+    U = np.asarray(u).reshape(p["ny"], p["nx"])
+    return np.array([4.0 / ((p["nx"] + 1) * (p["ny"] + 1)) *
+                     (np.sin(b * np.pi * y) @ U @ np.sin(a * np.pi * x)) for a, b in modes])
+
+
+@pytest.mark.parametrize("B", [64, 256])
+def test_cfg2_full_size_toeplitz_modal_parity(B, block_mode):
+    # 256^2, 20000 steps, in the launch configuration the benchmark times (B = 256, persistent)
+    w = W.cfg2()
+    p = w["problem"]
+    print_case(w["name"], "toeplitz", B, block_mode)
+    got = gpu_run(p, w["memory"], w["u0"], w["nsteps"], sum_path="toeplitz", block_B=B)
+    modes = [(1, 1), (1, 3), (3, 1), (3, 3), (2, 2), (1, 5), (5, 5)]
+    c0 = _modal(w["u0"], p, modes)
+    ref = np.array([c0[i] * oracle.mode_run(p, w["memory"], a, b, 1.0, w["nsteps"])[-1]
+                    for i, (a, b) in enumerate(modes)])
+    cg = _modal(got, p, modes)
+    assert np.abs(cg - ref).max() <= TOL_MFMA * np.abs(ref).max()
+
+
+def test_cfg2_sine_mode_full_size_toeplitz():
+    # a single sine mode on the 256^2 grid stays a sine mode: the whole field is known
+    w = W.cfg2()
+    p = w["problem"]
+    print_case("sine mode 256^2 toeplitz")
+    phi = W.sine_mode(p, 2, 3)
+    got = gpu_run(p, w["memory"], phi, w["nsteps"], sum_path="toeplitz")
+    v = oracle.mode_run(p, w["memory"], 2, 3, 1.0, w["nsteps"])
+    assert rel_l2(got, v[-1] * phi) <= TOL_MFMA
