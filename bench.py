@@ -70,15 +70,19 @@ def run_path(path, w, steps, warmup, block_B, prefix=True):
     macs = P * sum(terms)
     # algorithmic work of each kernel over one solve (see the design notes):
     #  hist_gemv: every history row of terms m >= 1 read once, 4 bytes per point
+    #  update:    u[k] read, u[k+1] and the FP32 history row k written (20 bytes per point)
     #  toeplitz:  6 flops (three BF16 products) per (block row, history row, point)
-    #  triangle:  the in-block rows m = 1..b, 4 bytes per point
-    #  update:    u read, u[k+1] and its FP32 history row written (+ the block sums read)
+    #  triangle:  one in-block step: rows m = 1..b (4 bytes each), u read and written,
+    #             history row written, the block sum read (8 bytes) after the first block
+    #  old_reduce: the FP32 chunk products read, the FP64 block sums written
     work = {"hist_gemv": ("hbm", 4 * P * sum(t - 1 for t in terms)),
-            "update": ("hbm", (20 + (8 if path == "toeplitz" else 0)) * P * n)}
+            "update": ("hbm", 20 * P * n)}
     if path == "toeplitz":
-        work["toeplitz"] = ("mfma", 6 * B * P * sum(k0 for k0 in range(B, n, B)))
-        work["triangle"] = ("hbm", 4 * P * sum(k % B for k in range(n)))
-        work["old_reduce"] = ("hbm", 8 * B * P * len(range(B, n, B)))
+        blocks = range(B, n, B)
+        work["toeplitz"] = ("mfma", 6 * B * P * sum(blocks))
+        work["triangle"] = ("hbm", P * sum(4 * (k % B) + 20 + (8 if k >= B else 0)
+                                           for k in range(n)))
+        work["old_reduce"] = ("hbm", B * P * sum(4 * -(-k0 // 2048) + 8 for k0 in blocks))
     for i in range(warmup):
         log(path, "warmup", i)
         s.reset(u0)

@@ -20,11 +20,10 @@
  *                            (Sec. 3.2, Def. 3.1, Def. 3.2, Prop. 3.1, eq. (24))
  *   f(u)     = 0, -rate u (eq. (18)), or rate u (1 - u) (Fisher-KPP).
  *
- * Because delta is linear, the library sums the stored states first and
- * applies the stencil once: sum c psi delta[k-m] = Lap(sum c psi u[k-m]).
- * The history of past states is kept in device memory as FP32 rows (one row
- * per step); the current state u[k], the weights and every per-step sum are
- * FP64.
+ * The history of the stencil values delta[j] of every past step is kept in
+ * device memory as FP32 rows (one row per step, as the sum of eq. (21) is
+ * written); the current state u[k], delta[k] itself, the weights and every
+ * per-step sum are FP64.
  *
  * Conventions for every entry point:
  *  - All array arguments are DEVICE pointers (e.g. torch CUDA tensors on the
@@ -162,7 +161,8 @@ gl_status gl_reset(gl_ctx *ctx, const double *u0);
 #define GL_KERNEL_HIST_GEMV 0    /* plain history sum (one launch per step and problem) */
 #define GL_KERNEL_UPDATE 1       /* stencil + reaction update */
 #define GL_KERNEL_TOEPLITZ 2     /* Toeplitz-weight x history product (one launch per block) */
-#define GL_KERNEL_TRIANGLE 3     /* in-block part of the blocked path's sums */
+#define GL_KERNEL_TRIANGLE 3     /* one step inside a block of the blocked path (rows in the
+                                    block, stencil, update: one launch per step) */
 #define GL_KERNEL_OLD_REDUCE 4   /* FP64 sum of the Toeplitz product's history chunks */
 #define GL_KERNEL_COUNT 5
 
@@ -191,7 +191,8 @@ gl_status gl_get_weights(gl_ctx *ctx, int32_t iprob, int64_t count, double *psi,
 int64_t gl_schedule_terms(const gl_ctx *ctx, int64_t k);
 
 /* The history sum alone, with the context's weights (problem iprob), memory
- * schedule and sum path, over a caller-supplied FP32 history:
+ * schedule and sum path, over a caller-supplied FP32 history (any rows, e.g.
+ * delta values):
  *   S[p] = sum_{(m,c) in sched(k)} c psi(gamma,m) hist[(k - m) * ld + p],
  * p = 0..P-1 (P = problem iprob's point count).  hist holds rows 0..k with
  * leading dimension ld >= P, ld % 4 == 0, 16-byte aligned.  S is FP64.

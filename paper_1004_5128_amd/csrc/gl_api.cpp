@@ -26,8 +26,6 @@ struct gl_ctx {
     double *partial = nullptr;  // kMaxSplits x max P (FP64)
     int *d_flag = nullptr;
     float *tpart = nullptr;  // Toeplitz product chunks: max chunks x B x max P (FP32)
-    double *Sblk = nullptr;  // in-block sums, 2 x max P (FP64)
-    int blk_capacity = 0;    // co-resident workgroups of the in-block kernel
     int B = 256;             // block length of the Toeplitz path
     gl::Tuning tune;
     std::vector<void *> allocs;
@@ -170,7 +168,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
         if (toep) need += 16 * (size_t)tab_len * sizeof(uint16_t) + (size_t)ctx->B * pb.P * sizeof(double);
     }
     need += (size_t)gl::kMaxSplits * maxP * sizeof(double);
-    if (toep) need += ((size_t)nchunk_max * ctx->B * maxP + 4 * (size_t)maxP) * sizeof(float);
+    if (toep) need += (size_t)nchunk_max * ctx->B * maxP * sizeof(float);
     size_t free_b = 0, total_b = 0;
     HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
     if (need + (size_t)(256u << 20) > free_b)
@@ -186,11 +184,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     if ((st = dev_alloc(ctx, &ctx->d_flag, 1))) return st;
     if (toep && (st = dev_alloc(ctx, &ctx->tpart, (size_t)std::max(nchunk_max, 1) * ctx->B * maxP)))
         return st;
-    if (toep && (st = dev_alloc(ctx, &ctx->Sblk, 2 * (size_t)maxP))) return st;
-    if (toep && ctx->tune.persistent) {
-        ctx->blk_capacity = gl::block_steps_capacity();
-        if (ctx->blk_capacity < 1) ctx->tune.persistent = false;
-    }
+
 
     for (gl::Problem &pb : ctx->probs) {
         if ((st = dev_alloc(ctx, &pb.psi, npsi))) return st;
@@ -275,8 +269,6 @@ gl_status load_initial(gl_ctx *ctx, const double *u0) {
         pb.old_k0 = -1;
         HIP_TRY(ctx, hipMemcpyAsync(pb.u[0], u0 + pb.offset, pb.P * sizeof(double),
                                     hipMemcpyDeviceToDevice, ctx->stream));
-        gl::launch_to_float(pb.u[0], pb.H, pb.P, ctx->stream);
-        HIP_TRY(ctx, hipGetLastError());
     }
     ctx->k = 0;
     HIP_TRY(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
@@ -309,7 +301,7 @@ gl_status step_gemv(gl_ctx *ctx) {
             if (st != GL_OK) return st;
         }
         st = timed(ctx, GL_KERNEL_UPDATE, [&] {
-            gl::launch_update(pb, u, nullptr, un, pb.H + (k + 1) * pb.ld, ctx->partial, nsplit,
+            gl::launch_update(pb, u, nullptr, un, pb.H + k * pb.ld, ctx->partial, nsplit,
                               ctx->stream);
         });
         if (st != GL_OK) return st;
@@ -335,89 +327,41 @@ gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld,
 }
 
 // One step k -> k + 1 on the blocked path: at the start of each block of B steps the
-// sums over the states before the block are formed by the Toeplitz product; each step
-// adds the states inside the block (terms m = 1..b, plain path) and psi(0) u[k].
+// sums over the states before the block are formed by the Toeplitz product; each step is
+// then one kernel (rows inside the block, stencil, update).
 gl_status step_toeplitz(gl_ctx *ctx) {
     const int64_t k = ctx->k;
     const int64_t b = k % ctx->B;
     const int64_t k0 = k - b;
-    const int64_t rb = ctx->sched.run_begin[k];
-    const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
     for (gl::Problem &pb : ctx->probs) {
         gl_status st;
         if (k0 > 0 && pb.old_k0 != k0) {
             if ((st = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old)) != GL_OK) return st;
             pb.old_k0 = k0;
         }
-        const double *u = pb.u[pb.cur];
-        double *un = pb.u[pb.cur ^ 1];
-        const int nsplit = gl::gemv_splits(b, pb.P, ctx->tune.gemv_groups);
-        if (nsplit > 0) {
-            st = timed(ctx, GL_KERNEL_TRIANGLE, [&] {
-                gl::launch_hist_gemv(pb.H, pb.ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 1,
-                                     b + 1, nsplit, false, ctx->partial, ctx->stream);
-            });
-            if (st != GL_OK) return st;
-        }
-        const double *base = k0 > 0 ? pb.old + b * pb.P : nullptr;
-        st = timed(ctx, GL_KERNEL_UPDATE, [&] {
-            gl::launch_update(pb, u, base, un, pb.H + (k + 1) * pb.ld, ctx->partial, nsplit,
-                              ctx->stream);
-        });
+        gl::BlockStepArgs args{};
+        args.psi = pb.psi;
+        args.H = pb.H;
+        args.ld = pb.ld;
+        args.P = pb.P;
+        args.ndim = pb.p.ndim;
+        args.nx = pb.p.nx;
+        args.ny = pb.p.ny;
+        args.rxn = pb.p.rxn;
+        args.r = pb.r;
+        args.dt = pb.p.dt;
+        args.rate = pb.p.rxn_rate;
+        args.old = k0 > 0 ? pb.old : nullptr;
+        args.u_cur = pb.u[pb.cur];
+        args.u_next = pb.u[pb.cur ^ 1];
+        args.k0 = k0;
+        args.b = (int32_t)b;
+        st = timed(ctx, GL_KERNEL_TRIANGLE, [&] { gl::launch_block_step(args, ctx->stream); });
         if (st != GL_OK) return st;
         pb.cur ^= 1;
     }
     HIP_TRY(ctx, hipGetLastError());
     ctx->k = k + 1;
-    return GL_OK;
-}
-
-// Runs up to n steps on the blocked path with one cooperative launch per block
-// segment: the Toeplitz product at each block start, then the in-block steps.
-gl_status steps_toeplitz_persistent(gl_ctx *ctx, int64_t n) {
-    while (n > 0) {
-        const int64_t k = ctx->k;
-        const int64_t b = k % ctx->B;
-        const int64_t k0 = k - b;
-        const int64_t seg = std::min<int64_t>(n, ctx->B - b);
-        for (gl::Problem &pb : ctx->probs) {
-            gl_status st;
-            if (k0 > 0 && pb.old_k0 != k0) {
-                if ((st = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old)) != GL_OK) return st;
-                pb.old_k0 = k0;
-            }
-            gl::BlockStepArgs args{};
-            args.psi = pb.psi;
-            args.H = pb.H;
-            args.ld = pb.ld;
-            args.P = pb.P;
-            args.ndim = pb.p.ndim;
-            args.nx = pb.p.nx;
-            args.ny = pb.p.ny;
-            args.rxn = pb.p.rxn;
-            args.r = pb.r;
-            args.dt = pb.p.dt;
-            args.rate = pb.p.rxn_rate;
-            args.old = k0 > 0 ? pb.old : nullptr;
-            args.u_cur = pb.u[pb.cur];
-            args.u_next = pb.u[pb.cur ^ 1];
-            args.S = ctx->Sblk;
-            args.k0 = k0;
-            args.b_begin = (int32_t)b;
-            args.b_end = (int32_t)(b + seg);
-            const int groups = gl::block_steps_groups(pb.P, ctx->blk_capacity);
-            hipError_t e = hipSuccess;
-            st = timed(ctx, GL_KERNEL_TRIANGLE,
-                       [&] { e = gl::launch_block_steps(args, groups, ctx->stream); });
-            if (st != GL_OK) return st;
-            if (e != hipSuccess)
-                return fail(ctx, GL_EHIP, "in-block cooperative launch failed: %s",
-                            hipGetErrorString(e));
-            if (seg & 1) pb.cur ^= 1;
-        }
-        ctx->k += seg;
-        n -= seg;
-    }
     return GL_OK;
 }
 
@@ -440,7 +384,6 @@ gl_status gl_init(const gl_problem *probs, int32_t nprob, const gl_options *opt,
     ctx->opt = *opt;
     if (const char *v = std::getenv("GL_GEMV_GROUPS")) ctx->tune.gemv_groups = std::max(1L, std::atol(v));
     if (const char *v = std::getenv("GL_GEMV_SERPENTINE")) ctx->tune.serpentine = std::atoi(v) != 0;
-    if (const char *v = std::getenv("GL_BLOCK_PERSISTENT")) ctx->tune.persistent = std::atoi(v) != 0;
     if (const char *v = std::getenv("GL_TOEPLITZ_KCHUNK"))
         ctx->tune.kchunk = std::max(64L, std::atol(v) / 64 * 64);
     ctx->stream = static_cast<hipStream_t>(opt->stream);
@@ -463,12 +406,8 @@ gl_status gl_step_n(gl_ctx *ctx, int64_t n, double *uT) {
                     (long long)ctx->k, (long long)n, (long long)ctx->opt.max_steps);
     gl_status st;
     const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
-    if (toep && ctx->tune.persistent) {
-        if ((st = steps_toeplitz_persistent(ctx, n)) != GL_OK) return st;
-    } else {
-        for (int64_t s = 0; s < n; ++s)
-            if ((st = toep ? step_toeplitz(ctx) : step_gemv(ctx)) != GL_OK) return st;
-    }
+    for (int64_t s = 0; s < n; ++s)
+        if ((st = toep ? step_toeplitz(ctx) : step_gemv(ctx)) != GL_OK) return st;
     if (uT && (st = copy_state(ctx, uT)) != GL_OK) return st;
     if (ctx->opt.check_finite) {
         HIP_TRY(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));

@@ -43,7 +43,7 @@ struct Problem {
     int64_t offset = 0;   // first point of this problem in concatenated arrays
     double *psi = nullptr;   // [max_steps + 1] FP64 weights
     double *dpsi = nullptr;  // [max_steps + 1] d psi / d gamma
-    float *H = nullptr;      // [(max_steps + 1) * ld] FP32 history, row j = u[j]
+    float *H = nullptr;      // [(max_steps + 1) * ld] FP32 history, row j = delta[j] (eq. 17)
     double *u[2] = {nullptr, nullptr};  // FP64 state, double-buffered
     int cur = 0;             // u[cur] holds the current step
     // blocked Toeplitz path
@@ -73,13 +73,12 @@ void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, 
                       int nruns, int64_t k, int64_t t_begin, int64_t t_end, int nsplit,
                       bool reverse, double *partial, hipStream_t s);
 
-// Tuning (defaults; GL_GEMV_GROUPS, GL_GEMV_SERPENTINE, GL_TOEPLITZ_KCHUNK and
-// GL_BLOCK_PERSISTENT in the environment override them at gl_init).
+// Tuning (defaults; GL_GEMV_GROUPS, GL_GEMV_SERPENTINE and GL_TOEPLITZ_KCHUNK in
+// the environment override them at gl_init).
 struct Tuning {
     int64_t gemv_groups = 1024;  // target workgroups per GEMV launch
     bool serpentine = false;     // alternate the traversal direction every step
     int64_t kchunk = 2048;       // history rows per Toeplitz product chunk (multiple of 64)
-    bool persistent = true;      // in-block steps as one cooperative launch per block
 };
 
 // ---- blocked Toeplitz path
@@ -102,8 +101,7 @@ void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const u
 void launch_old_reduce(const float *part, int nchunk, int64_t BM, int64_t P, double *old,
                        hipStream_t s);
 
-// Arguments of the persistent in-block kernel: steps k0 + b for b in [b_begin, b_end)
-// of one problem, u_cur holding u[k0 + b_begin].
+// Arguments of the in-block step kernel: step k0 + b of one problem.
 struct BlockStepArgs {
     const double *psi;
     float *H;
@@ -111,30 +109,24 @@ struct BlockStepArgs {
     int32_t ndim, nx, ny, rxn;
     double r, dt, rate;
     const double *old;  // [B x P] sums over the states before the block, or nullptr (k0 = 0)
-    double *u_cur, *u_next;
-    double *S;          // [2 x P] scratch, double-buffered by step parity
+    const double *u_cur;
+    double *u_next;
     int64_t k0;
-    int32_t b_begin, b_end;
+    int32_t b;
 };
 
-// Maximum co-resident workgroups of the in-block kernel on the current device.
-int block_steps_capacity();
-// Workgroups used for P points (<= capacity).
-int block_steps_groups(int64_t P, int capacity);
-// One cooperative launch running the steps of `args`.
-hipError_t launch_block_steps(const BlockStepArgs &args, int groups, hipStream_t s);
+// One in-block step as a single kernel (history sum over rows k0..k-1, stencil,
+// reaction, state update, history row k).
+void launch_block_step(const BlockStepArgs &args, hipStream_t s);
 
 // S[p] = sum_s partial[s * P + p] (+ base[p] if base != nullptr), fixed order.
 void launch_reduce_partials(const double *partial, int nsplit, int64_t P, const double *base,
                             double *S, hipStream_t s);
 
-// One explicit step: S = u (+ base) + sum_s partial[s]; unew = u + dt f(u) + r Lap(S);
-// Hnext = (float) unew.  base (nullable) holds the sum over states before the block.
+// One explicit step after the GEMV: d = stencil(u); S = d (+ base) + sum_s partial[s];
+// unew = u + dt f(u) + r S; Hk (history row k) = (float) d.
 void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
-                   float *Hnext, const double *partial, int nsplit, hipStream_t s);
-
-// h[p] = (float) u[p]
-void launch_to_float(const double *u, float *h, int64_t n, hipStream_t s);
+                   float *Hk, const double *partial, int nsplit, hipStream_t s);
 
 // *flag = 1 if any of x[0..n) is NaN or Inf (flag must start at 0).
 void launch_check_finite(const double *x, int64_t n, int *flag, hipStream_t s);

@@ -167,16 +167,12 @@ void launch_reduce_partials(const double *partial, int nsplit, int64_t P, const 
 
 // ------------------------------------------------------------------ update
 //
-// One step of eq. (21) after the history sum: with S = u[k] + sum of the
-// GEMV partials (the m = 0 term psi(0) u[k] = u[k] is taken from the FP64
-// state), u[k+1] = u[k] + dt f(u[k]) + r Lap(S), Lap the un-normalised 5-point
-// (2D) or 3-point (1D) stencil of eq. (17) with zero values outside the grid.
-// A 2D workgroup updates a 32 x 8 tile; it first forms S on the tile plus a
-// one-point halo in LDS (recomputing the halo from the partials), then applies
-// the stencil from LDS.
-
-constexpr int kTileX = 32;
-constexpr int kTileY = 8;
+// One step of eq. (21) once the history sum over m >= 1 is in the GEMV
+// partials: delta[k] = the un-normalised stencil of eq. (17) (zero values
+// outside the grid) of the FP64 state u[k]; S = psi(0) delta[k] (+ base) +
+// sum of the partials in split order; u[k+1] = u[k] + dt f(u[k]) + r S.  The
+// history row k receives delta[k] in FP32.  One lane per point; the stencil
+// reads the neighbours' FP64 state.
 
 __device__ __forceinline__ double reaction(int rxn, double rate, double u) {
     if (rxn == GL_RXN_LINEAR) return -rate * u;
@@ -184,15 +180,32 @@ __device__ __forceinline__ double reaction(int rxn, double rate, double u) {
     return 0.0;
 }
 
-__device__ __forceinline__ double sum_at(const double *__restrict__ u,
-                                         const double *__restrict__ base,
-                                         const double *__restrict__ partial, int nsplit,
-                                         int64_t P, int64_t p) {
-    // loads issued eight at a time, added in split order (fixed rounding)
-    double s = u[p];
+__device__ __forceinline__ double stencil_at(const double *__restrict__ u, int64_t p, int ndim,
+                                             int nx, int ny) {
+    if (ndim == 1) {
+        const double e = p + 1 < nx ? u[p + 1] : 0.0;
+        const double w = p > 0 ? u[p - 1] : 0.0;
+        return e - 2.0 * u[p] + w;
+    }
+    const int64_t x = p % nx, y = p / nx;
+    const double e = x + 1 < nx ? u[p + 1] : 0.0;
+    const double w = x > 0 ? u[p - 1] : 0.0;
+    const double n = y + 1 < ny ? u[p + nx] : 0.0;
+    const double s = y > 0 ? u[p - nx] : 0.0;
+    return e + w - 4.0 * u[p] + n + s;
+}
+
+__global__ __launch_bounds__(256) void update_kernel(
+    const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
+    float *__restrict__ Hk, const double *__restrict__ partial, int nsplit, int64_t P, int ndim,
+    int nx, int ny, double r, double dt, int rxn, double rate) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double d = stencil_at(u, p, ndim, nx, ny);
+    double s = d;
     if (base) s += base[p];
     int q = 0;
-    for (; q + 8 <= nsplit; q += 8) {
+    for (; q + 8 <= nsplit; q += 8) {  // loads issued eight at a time, added in split order
         double v[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = partial[(int64_t)(q + i) * P + p];
@@ -200,86 +213,20 @@ __device__ __forceinline__ double sum_at(const double *__restrict__ u,
         for (int i = 0; i < 8; ++i) s += v[i];
     }
     for (; q < nsplit; ++q) s += partial[(int64_t)q * P + p];
-    return s;
-}
-
-__global__ __launch_bounds__(kTileX *kTileY) void update2d_kernel(
-    const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
-    float *__restrict__ Hnext,
-    const double *__restrict__ partial, int nsplit, int nx, int ny, double r, double dt, int rxn,
-    double rate) {
-    __shared__ double S[kTileY + 2][kTileX + 2];
-    const int64_t P = (int64_t)nx * ny;
-    const int x0 = blockIdx.x * kTileX, y0 = blockIdx.y * kTileY;
-    for (int i = threadIdx.x; i < (kTileX + 2) * (kTileY + 2); i += kTileX * kTileY) {
-        const int ly = i / (kTileX + 2), lx = i % (kTileX + 2);
-        const int gx = x0 + lx - 1, gy = y0 + ly - 1;
-        double s = 0.0;
-        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny)
-            s = sum_at(u, base, partial, nsplit, P, (int64_t)gy * nx + gx);
-        S[ly][lx] = s;
-    }
-    __syncthreads();
-    const int lx = threadIdx.x % kTileX, ly = threadIdx.x / kTileX;
-    const int gx = x0 + lx, gy = y0 + ly;
-    if (gx >= nx || gy >= ny) return;
-    const int64_t p = (int64_t)gy * nx + gx;
-    const double lap = S[ly + 1][lx + 2] + S[ly + 1][lx] - 4.0 * S[ly + 1][lx + 1] +
-                       S[ly + 2][lx + 1] + S[ly][lx + 1];
     const double uk = u[p];
-    const double un = uk + dt * reaction(rxn, rate, uk) + r * lap;
-    unew[p] = un;
-    Hnext[p] = (float)un;
-}
-
-constexpr int kTile1 = 256;
-
-__global__ __launch_bounds__(kTile1) void update1d_kernel(
-    const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
-    float *__restrict__ Hnext,
-    const double *__restrict__ partial, int nsplit, int nx, double r, double dt, int rxn,
-    double rate) {
-    __shared__ double S[kTile1 + 2];
-    const int x0 = blockIdx.x * kTile1;
-    for (int i = threadIdx.x; i < kTile1 + 2; i += kTile1) {
-        const int gx = x0 + i - 1;
-        S[i] = (gx >= 0 && gx < nx) ? sum_at(u, base, partial, nsplit, nx, gx) : 0.0;
-    }
-    __syncthreads();
-    const int gx = x0 + threadIdx.x;
-    if (gx >= nx) return;
-    const int lx = threadIdx.x + 1;
-    const double lap = S[lx + 1] - 2.0 * S[lx] + S[lx - 1];
-    const double uk = u[gx];
-    const double un = uk + dt * reaction(rxn, rate, uk) + r * lap;
-    unew[gx] = un;
-    Hnext[gx] = (float)un;
+    unew[p] = uk + dt * reaction(rxn, rate, uk) + r * s;
+    Hk[p] = (float)d;
 }
 
 void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
-                   float *Hnext, const double *partial, int nsplit, hipStream_t s) {
+                   float *Hk, const double *partial, int nsplit, hipStream_t s) {
     const gl_problem &p = pb.p;
-    if (p.ndim == 1) {
-        hipLaunchKernelGGL(update1d_kernel, dim3((unsigned)((p.nx + kTile1 - 1) / kTile1)),
-                           dim3(kTile1), 0, s, u, base, unew, Hnext, partial, nsplit, p.nx, pb.r,
-                           p.dt, p.rxn, p.rxn_rate);
-    } else {
-        dim3 grid((unsigned)((p.nx + kTileX - 1) / kTileX), (unsigned)((p.ny + kTileY - 1) / kTileY));
-        hipLaunchKernelGGL(update2d_kernel, grid, dim3(kTileX * kTileY), 0, s, u, base, unew,
-                           Hnext, partial, nsplit, p.nx, p.ny, pb.r, p.dt, p.rxn, p.rxn_rate);
-    }
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)((pb.P + 255) / 256)), dim3(256), 0, s, u,
+                       base, unew, Hk, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, pb.r, p.dt,
+                       p.rxn, p.rxn_rate);
 }
 
 // ----------------------------------------------------------------- helpers
-
-__global__ void to_float_kernel(const double *__restrict__ u, float *__restrict__ h, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) h[i] = (float)u[i];
-}
-
-void launch_to_float(const double *u, float *h, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(to_float_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, u, h, n);
-}
 
 __global__ void check_finite_kernel(const double *__restrict__ x, int64_t n, int *flag) {
     bool bad = false;

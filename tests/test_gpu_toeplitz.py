@@ -1,8 +1,6 @@
 """Parity of the blocked Toeplitz path (history before each block of B steps summed as
-one BF16 hi/lo x 3 matrix product with FP32 accumulation, FP64 chunk sums; the rest on
-the plain path) with the FP64 oracle.  Tolerance: relative L2 <= 1e-5."""
-import os
-
+one BF16 hi/lo x 3 matrix product with FP32 accumulation, FP64 chunk sums; each step
+inside the block one kernel) with the FP64 oracle.  Tolerance: relative L2 <= 1e-5."""
 import numpy as np
 import pytest
 import torch
@@ -14,18 +12,6 @@ from gpu_util import gl, gpu_run, print_case, rel_l2
 pytestmark = pytest.mark.gpu
 
 TOL_MFMA = 1e-5
-
-
-@pytest.fixture(params=["persistent", "per_step"])
-def block_mode(request):
-    """In-block steps as one cooperative launch per block, or two launches per step."""
-    old = os.environ.get("GL_BLOCK_PERSISTENT")
-    os.environ["GL_BLOCK_PERSISTENT"] = "1" if request.param == "persistent" else "0"
-    yield request.param
-    if old is None:
-        del os.environ["GL_BLOCK_PERSISTENT"]
-    else:
-        os.environ["GL_BLOCK_PERSISTENT"] = old
 
 
 @pytest.mark.parametrize("B", [32, 64, 128, 256])
@@ -74,39 +60,39 @@ def test_block_history_sum_full_depth():
             assert np.abs(got - ref).max() <= TOL_MFMA * scale
 
 
-def test_cfg1_toeplitz_matches_oracle(block_mode):
+def test_cfg1_toeplitz_matches_oracle():
     w = W.cfg1()
-    print_case(w["name"], "toeplitz", block_mode)
+    print_case(w["name"], "toeplitz")
     got = gpu_run(w["problem"], w["memory"], w["u0"], w["nsteps"], sum_path="toeplitz")
     ref = oracle.run(w["problem"], w["memory"], w["u0"], w["nsteps"])
     assert rel_l2(got, ref) <= TOL_MFMA
 
 
 @pytest.mark.parametrize("B", [32, 64, 128, 256])
-def test_2d_reduced_cfg2_toeplitz_matches_oracle(B, block_mode):
+def test_2d_reduced_cfg2_toeplitz_matches_oracle(B):
     w = W.cfg2(n=64, nsteps=1100)
-    print_case(w["name"], "toeplitz", B, block_mode)
+    print_case(w["name"], "toeplitz", B)
     got = gpu_run(w["problem"], w["memory"], w["u0"], w["nsteps"], sum_path="toeplitz", block_B=B)
     ref = oracle.run(w["problem"], w["memory"], w["u0"], w["nsteps"])
     assert rel_l2(got, ref) <= TOL_MFMA
 
 
 @pytest.mark.parametrize("shape", [(48, 48), (37, 23), (1, 1), (130, 3)])
-def test_fisher_ragged_toeplitz_matches_oracle(shape, block_mode):
+def test_fisher_ragged_toeplitz_matches_oracle(shape):
     p = W.problem(2, shape[0], 0.6, 0.5, 0.1, rxn="fisher", rate=1.0)
     p["ny"] = shape[1]
     u0 = W.uniform_field(p, 3)
     n = 700
-    print_case("fisher toeplitz", shape, block_mode)
+    print_case("fisher toeplitz", shape)
     got = gpu_run(p, W.memory("full"), u0, n, sum_path="toeplitz", block_B=64)
     ref = oracle.run(p, W.memory("full"), u0, n)
     assert rel_l2(got, ref) <= TOL_MFMA
 
 
-def test_split_calls_equal_one_call(block_mode):
+def test_split_calls_equal_one_call():
     # stopping inside a block and continuing gives the same bits as one call
     w = W.cfg2(n=40, nsteps=600)
-    print_case("toeplitz split calls", block_mode)
+    print_case("toeplitz split calls")
     G = gl()
     u0 = torch.as_tensor(w["u0"])
     with G.Solver(w["problem"], w["memory"], u0, max_steps=600, sum_path="toeplitz",
@@ -127,21 +113,6 @@ def test_toeplitz_needs_full_memory():
     assert e.value.status == G.GL_EUNSUPPORTED
 
 
-def test_persistent_and_per_step_agree():
-    # the two in-block schedules differ only in summation order
-    w = W.cfg2(n=96, nsteps=900)
-    outs = []
-    for mode in ("1", "0"):
-        os.environ["GL_BLOCK_PERSISTENT"] = mode
-        try:
-            print_case("persistent", mode)
-            outs.append(gpu_run(w["problem"], w["memory"], w["u0"], w["nsteps"],
-                                sum_path="toeplitz", block_B=128))
-        finally:
-            del os.environ["GL_BLOCK_PERSISTENT"]
-    assert rel_l2(outs[0], outs[1]) <= 1e-12
-
-
 def _modal(u, p, modes):
     x, y = W.coords(p["nx"]), W.coords(p["ny"])
     U = np.asarray(u).reshape(p["ny"], p["nx"])
@@ -150,11 +121,11 @@ def _modal(u, p, modes):
 
 
 @pytest.mark.parametrize("B", [64, 256])
-def test_cfg2_full_size_toeplitz_modal_parity(B, block_mode):
-    # 256^2, 20000 steps, in the launch configuration the benchmark times (B = 256, persistent)
+def test_cfg2_full_size_toeplitz_modal_parity(B):
+    # 256^2, 20000 steps, in the launch configuration the benchmark times (B = 256)
     w = W.cfg2()
     p = w["problem"]
-    print_case(w["name"], "toeplitz", B, block_mode)
+    print_case(w["name"], "toeplitz", B)
     got = gpu_run(p, w["memory"], w["u0"], w["nsteps"], sum_path="toeplitz", block_B=B)
     modes = [(1, 1), (1, 3), (3, 1), (3, 3), (2, 2), (1, 5), (5, 5)]
     c0 = _modal(w["u0"], p, modes)
