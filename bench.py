@@ -58,31 +58,112 @@ def copy_calibration(nbytes=1 << 30, reps=3):
     log("copy calibration: %d x %d bytes read + written" % (reps, nbytes))
 
 
-def run_path(path, w, steps, warmup, block_B, prefix=True):
+def source_sha(kernel):
+    """SHA-256 of the HIP source holding a kernel (traffic counters are tied to it)."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_1004_5128_amd", "csrc", KERNEL_SOURCES[kernel])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+KERNEL_SOURCES = {"hist_gemv": "gl_kernels.hip", "update": "gl_kernels.hip",
+                  "toeplitz": "gl_toeplitz.hip", "old_reduce": "gl_toeplitz.hip",
+                  "triangle": "gl_block.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+
+
+def measured_traffic():
+    """{kernel: HBM bytes / algorithmic bytes} from the committed counter summary, for
+    kernels whose source is unchanged since the counters were taken."""
+    out = {}
+    if not os.path.exists(TRAFFIC_FILE):
+        return out
+    for line in open(TRAFFIC_FILE):
+        if line.startswith("kernel="):
+            kv = dict(tok.split("=", 1) for tok in line.split())
+            if kv.get("source_sha") == source_sha(kv["kernel"]):
+                out[kv["kernel"]] = float(kv["traffic_over_algorithmic"])
+    return out
+
+
+ROCPROF_NAMES = {"gl::hist_gemv_kernel": "hist_gemv", "gl::update_kernel": "update",
+                 "gl::toeplitz_gemm_kernel": "toeplitz", "gl::old_reduce_kernel": "old_reduce",
+                 "gl::block_step_kernel": "triangle"}
+
+
+def summarize_counters(fetch_csv, write_csv, work):
+    """Lines of the traffic summary from two rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE, KiB
+    per dispatch) of a --profile-steps run with --copy-calibration; `work` is that run's
+    algorithmic work.  Each counter is scaled by what it reads for the 1 GiB device copy."""
+    import collections
+    import csv
+
+    def per_kernel(path, counter):
+        vals, copies = collections.defaultdict(list), []
+        for row in csv.DictReader(open(path)):
+            if row["Counter_Name"] != counter:
+                continue
+            v = float(row["Counter_Value"])
+            if "copyBuffer" in row["Kernel_Name"] and int(row["Grid_Size"]) >= 131072:
+                copies.append(v)
+            for prefix, name in ROCPROF_NAMES.items():
+                if prefix in row["Kernel_Name"].replace("void ", ""):
+                    vals[name].append(v)
+        return vals, copies
+
+    fetch, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
+    write, wcopy = per_kernel(write_csv, "WRITE_SIZE")
+    gib_kib = float(1 << 20)
+    ff, wf = (sum(fcopy) / len(fcopy)) / gib_kib, (sum(wcopy) / len(wcopy)) / gib_kib
+    lines = ["# copy calibration: a 1 GiB device copy reads FETCH_SIZE %.4f GiB, WRITE_SIZE %.4f GiB"
+             % (ff, wf)]
+    for name in sorted(fetch):
+        n = len(fetch[name])
+        hbm = (sum(fetch[name]) / n / ff + sum(write[name]) / len(write[name]) / wf) * 1024
+        kind, w = work.get(name + "_bytes", work.get(name, (None, None)))
+        if kind != "hbm":
+            continue
+        alg = w / n
+        lines.append("kernel=%s source_sha=%s launches=%d fetch_kib_per_launch=%.1f "
+                     "write_kib_per_launch=%.1f hbm_bytes_per_launch=%.0f "
+                     "algorithmic_bytes_per_launch=%.0f traffic_over_algorithmic=%.4f"
+                     % (name, source_sha(name), n, sum(fetch[name]) / n,
+                        sum(write[name]) / len(write[name]), hbm, alg, hbm / alg))
+    return lines
+
+
+def algorithmic_work(path, P, n, B, terms):
+    """Algorithmic work of each kernel over one solve of n steps (see the design notes):
+     hist_gemv:  every history row of terms m >= 1 read once, 4 bytes per point
+     update:     u[k] read, u[k+1] and the FP32 history row k written (20 bytes per point)
+     toeplitz:   6 flops (three BF16 products) per (block row, history row, point); its HBM
+                 side: history rows read once, FP32 chunk products written
+     triangle:   one in-block step: rows m = 1..b (4 bytes each), u read and written, history
+                 row written, the block sum read (8 bytes) after the first block
+     old_reduce: the FP32 chunk products read, the FP64 block sums written"""
+    work = {"hist_gemv": ("hbm", 4 * P * sum(t - 1 for t in terms)),
+            "update": ("hbm", 20 * P * n)}
+    if path == "toeplitz":
+        blocks = range(B, n, B)
+        work["toeplitz"] = ("mfma", 6 * B * P * sum(blocks))
+        work["toeplitz_bytes"] = ("hbm", P * sum(4 * k0 + 4 * B * -(-k0 // 2048) for k0 in blocks))
+        work["triangle"] = ("hbm", P * sum(4 * (k % B) + 20 + (8 if k >= B else 0)
+                                           for k in range(n)))
+        work["old_reduce"] = ("hbm", B * P * sum(4 * -(-k0 // 2048) + 8 for k0 in blocks))
+    return work
+
+
+def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
     import torch
     from paper_1004_5128_amd import gl
-    p, n = w["problem"], w["nsteps"]
+    p = w["problem"]
+    n = nsteps or w["nsteps"]
     P = gl.npoints(p)
     u0 = torch.as_tensor(w["u0"], dtype=torch.float64).cuda()
     s = gl.Solver(p, w["memory"], u0, max_steps=n, sum_path=path, block_B=block_B)
     B = block_B or 256
     terms = [s.schedule_terms(k) for k in range(n)]
     macs = P * sum(terms)
-    # algorithmic work of each kernel over one solve (see the design notes):
-    #  hist_gemv: every history row of terms m >= 1 read once, 4 bytes per point
-    #  update:    u[k] read, u[k+1] and the FP32 history row k written (20 bytes per point)
-    #  toeplitz:  6 flops (three BF16 products) per (block row, history row, point)
-    #  triangle:  one in-block step: rows m = 1..b (4 bytes each), u read and written,
-    #             history row written, the block sum read (8 bytes) after the first block
-    #  old_reduce: the FP32 chunk products read, the FP64 block sums written
-    work = {"hist_gemv": ("hbm", 4 * P * sum(t - 1 for t in terms)),
-            "update": ("hbm", 20 * P * n)}
-    if path == "toeplitz":
-        blocks = range(B, n, B)
-        work["toeplitz"] = ("mfma", 6 * B * P * sum(blocks))
-        work["triangle"] = ("hbm", P * sum(4 * (k % B) + 20 + (8 if k >= B else 0)
-                                           for k in range(n)))
-        work["old_reduce"] = ("hbm", B * P * sum(4 * -(-k0 // 2048) + 8 for k0 in blocks))
+    work = algorithmic_work(path, P, n, B, terms)
     for i in range(warmup):
         log(path, "warmup", i)
         s.reset(u0)
@@ -136,7 +217,22 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 1 GiB device copy (reference for traffic counters)")
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="short run for counter collection: one solve of this many steps per "
+                         "path, no warmup, no oracle")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the traffic summary lines from the counter CSVs of a "
+                         "--profile-steps run of the given --paths (no GPU)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        from paper_1004_5128_amd import workloads as W
+        w = W.cfg2()
+        n = args.profile_steps or w["nsteps"]
+        for path in [x for x in args.paths.split(",") if x]:
+            work = algorithmic_work(path, W.npoints(w["problem"]), n, args.block_B or 256,
+                                    [k + 1 for k in range(n)])
+            print("\n".join(summarize_counters(*args.summarize_counters, work)))
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the solver runs on a single "
               "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -152,11 +248,15 @@ def main():
     if args.copy_calibration:
         copy_calibration()
     paths = [x for x in args.paths.split(",") if x]
-    res = {path: run_path(path, w, args.steps, args.warmup, args.block_B, prefix=not args.no_cpu)
+    if args.profile_steps:
+        args.no_cpu, args.steps, args.warmup = True, 1, 0
+    res = {path: run_path(path, w, args.steps, args.warmup, args.block_B, prefix=not args.no_cpu,
+                          nsteps=args.profile_steps or None)
            for path in paths}
     primary = paths[-1]
 
     out_paths = {}
+    traffic = measured_traffic()
     oracle_prefix = oracle_modal = None
     cpu = None
     if not args.no_cpu:
@@ -183,6 +283,12 @@ def main():
                 if name in r["work"]:
                     kind, work = r["work"][name]
                     kd["roofline"] = roofline_of(kind, work, cnt / r["steps"], ms / r["steps"])
+                    # algorithmic HBM bytes per launch (for MFMA kernels: their memory side)
+                    hbm = r["work"].get(name + "_bytes", (None, work if kind == "hbm" else None))[1]
+                    if hbm is not None:
+                        kd["roofline"]["algorithmic_bytes_per_launch"] = hbm * r["steps"] / cnt
+                        if name in traffic:
+                            kd["roofline"]["traffic"] = traffic[name] * hbm * r["steps"] / cnt
                 d.setdefault("kernels", {})[name] = kd
         if oracle_prefix is not None:
             d["rel_l2_vs_oracle_prefix"] = float(np.linalg.norm(r["u_prefix"] - oracle_prefix) /
@@ -210,7 +316,8 @@ def main():
         "dtype": "bf16x3 mfma (f32 acc) + f64" if primary == "toeplitz" else "f32 history, f64 accumulate",
         "data": "synthetic",
         "config": {"workload": "2d_256x256_gamma0.8_alpha1_linear0.1_gaussian_r0.1_20000steps_full",
-                   "grid": [p["nx"], p["ny"]], "time_steps": n, "memory": "full",
+                   "grid": [p["nx"], p["ny"]], "time_steps": args.profile_steps or n,
+                   "memory": "full",
                    "history_macs_per_solve": r["macs"], "path": primary},
         "paths": out_paths,
         "roofline": roofline,

@@ -42,6 +42,10 @@ struct gl_ctx {
     double prof_ms[GL_KERNEL_COUNT] = {};
 };
 
+namespace gl {
+thread_local KernelTimer g_kernel_timer;
+}
+
 namespace {
 
 thread_local std::string g_thread_err;
@@ -241,7 +245,8 @@ gl_status resolve_profile(gl_ctx *ctx) {
     return GL_OK;
 }
 
-// Runs launch() and, in profiling mode, brackets it with events on the stream.
+// Runs launch() (exactly one kernel launch) and, in profiling mode, has the runtime stamp
+// a start and a stop event at that kernel's own start and end.
 template <class F>
 gl_status timed(gl_ctx *ctx, int kernel, F &&launch) {
     if (!ctx->prof) {
@@ -251,9 +256,10 @@ gl_status timed(gl_ctx *ctx, int kernel, F &&launch) {
     gl_ctx::Pending pd{kernel, nullptr, nullptr};
     gl_status st;
     if ((st = take_event(ctx, &pd.start)) || (st = take_event(ctx, &pd.stop))) return st;
-    HIP_TRY(ctx, hipEventRecord(pd.start, ctx->stream));
+    gl::g_kernel_timer = gl::KernelTimer{pd.start, pd.stop};
     launch();
-    HIP_TRY(ctx, hipEventRecord(pd.stop, ctx->stream));
+    gl::g_kernel_timer = gl::KernelTimer{};
+    HIP_TRY(ctx, hipGetLastError());
     ctx->pending.push_back(pd);
     if (ctx->pending.size() >= 4096) {
         HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kStepThreads) void block_step_kernel(BlockStepArgs 
 
 void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
     const unsigned groups = (unsigned)((args.P + kStepPoints - 1) / kStepPoints);
-    hipLaunchKernelGGL(block_step_kernel, dim3(groups), dim3(kStepThreads), 0, s, args);
+    GL_LAUNCH(block_step_kernel, dim3(groups), dim3(kStepThreads), 0, s, args);
 }
 
 }  // namespace gl

@@ -2,6 +2,7 @@
 // schedule tables and the kernel launchers.  Not part of the C ABI.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -11,6 +12,24 @@
 #include "gl.h"
 
 namespace gl {
+
+// Events the profiling mode wants stamped when the next kernel launched on this thread
+// starts and ends (hipExtLaunchKernelGGL records them at the kernel's own start and end,
+// so the interval excludes the dispatch gap).  Null: plain launch.
+struct KernelTimer {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+extern thread_local KernelTimer g_kernel_timer;
+
+#define GL_LAUNCH(kernel, grid, block, shmem, stream, ...)                                      \
+    do {                                                                                        \
+        if (::gl::g_kernel_timer.start)                                                         \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, ::gl::g_kernel_timer.start, \
+                                  ::gl::g_kernel_timer.stop, 0, __VA_ARGS__);                   \
+        else                                                                                    \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                \
+    } while (0)
 
 // One run of schedule terms: offsets m = m0 + i * stride (i = 0..count-1), each
 // entering the history sum with weight coef * psi(gamma, m).  A step's runs are

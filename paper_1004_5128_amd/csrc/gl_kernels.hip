@@ -31,7 +31,7 @@ __global__ void weights_kernel(double gamma, int64_t n, double *__restrict__ psi
 }
 
 void launch_weights(double gamma, int64_t n, double *psi, double *dpsi, hipStream_t s) {
-    hipLaunchKernelGGL(weights_kernel, dim3(1), dim3(64), 0, s, gamma, n, psi, dpsi);
+    GL_LAUNCH(weights_kernel, dim3(1), dim3(64), 0, s, gamma, n, psi, dpsi);
 }
 
 // ------------------------------------------------------------ history GEMV
@@ -146,7 +146,7 @@ void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, 
                       int nruns, int64_t k, int64_t t_begin, int64_t t_end, int nsplit,
                       bool reverse, double *partial, hipStream_t s) {
     const unsigned colblocks = (unsigned)((P + kGemvCols - 1) / kGemvCols);
-    hipLaunchKernelGGL(hist_gemv_kernel, dim3(colblocks, (unsigned)nsplit), dim3(kGemvThreads), 0,
+    GL_LAUNCH(hist_gemv_kernel, dim3(colblocks, (unsigned)nsplit), dim3(kGemvThreads), 0,
                        s, H, ld, P, psi, runs, nruns, k, t_begin, t_end, reverse ? 1 : 0, partial);
 }
 
@@ -161,7 +161,7 @@ __global__ void reduce_partials_kernel(const double *__restrict__ partial, int n
 
 void launch_reduce_partials(const double *partial, int nsplit, int64_t P, const double *base,
                             double *S, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s,
+    GL_LAUNCH(reduce_partials_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s,
                        partial, nsplit, P, base, S);
 }
 
@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void update_kernel(
 void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
                    float *Hk, const double *partial, int nsplit, hipStream_t s) {
     const gl_problem &p = pb.p;
-    hipLaunchKernelGGL(update_kernel, dim3((unsigned)((pb.P + 255) / 256)), dim3(256), 0, s, u,
+    GL_LAUNCH(update_kernel, dim3((unsigned)((pb.P + 255) / 256)), dim3(256), 0, s, u,
                        base, unew, Hk, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, pb.r, p.dt,
                        p.rxn, p.rxn_rate);
 }
@@ -240,7 +240,7 @@ void launch_check_finite(const double *x, int64_t n, int *flag, hipStream_t s) {
     int64_t blocks = (n + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
+    GL_LAUNCH(check_finite_kernel, dim3((unsigned)blocks), dim3(256), 0, s, x, n, flag);
 }
 
 }  // namespace gl

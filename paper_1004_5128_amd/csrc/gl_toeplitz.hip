@@ -1,20 +1,21 @@
 // Blocked Toeplitz history sum on gfx950 BF16 matrix cores.
 //
-// With full memory (Sec. 2.2, eq. (21)) step k sums psi(gamma, k - j) u[j] over
-// every stored state j <= k.  For a block of B consecutive steps k = k0 + b
-// (b = 0..B-1) the part over the states before the block,
+// With full memory (Sec. 2.2, eq. (21)) step k sums psi(gamma, k - j) delta[j]
+// over every past step j <= k, delta[j] the stencil of eq. (17) kept as FP32
+// history rows H[j].  For a block of B consecutive steps k = k0 + b
+// (b = 0..B-1) the part over the rows before the block,
 //
 //     Old[b, p] = sum_{j < k0} psi(gamma, k0 + b - j) H[j, p],
 //
 // is a matrix product T H with the Toeplitz weight matrix T[b, j] =
-// psi(k0 + b - j) (B x k0) and the FP32 history H (k0 x P).  It is computed once
+// psi(k0 + b - j) (B x k0) and the history H (k0 x P).  It is computed once
 // per block on the matrix cores with each operand split into two BF16 parts,
 // x = hi + lo (hi = x rounded to BF16, lo = the remainder rounded to BF16), and
 // three products hi.hi + hi.lo + lo.hi accumulated in FP32; the history rows are
 // split on the fly, the weights come from precomputed split tables.  The
 // history dimension is cut into chunks whose FP32 partial products are summed in
 // FP64, in chunk order, by a second kernel.  The rest of each step's sum (the
-// states inside the block) is summed by the plain path.
+// rows inside the block) is added by the in-block step kernel.
 #include <hip/hip_runtime.h>
 
 #include "gl_internal.h"
@@ -55,7 +56,7 @@ __global__ void psi_tables_kernel(const double *__restrict__ psi, int64_t npsi, 
 void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_t *tab,
                        hipStream_t s) {
     dim3 grid((unsigned)((tab_len + 255) / 256), 8);
-    hipLaunchKernelGGL(psi_tables_kernel, grid, dim3(256), 0, s, psi, npsi, tab_len, tab);
+    GL_LAUNCH(psi_tables_kernel, grid, dim3(256), 0, s, psi, npsi, tab_len, tab);
 }
 
 // --------------------------------------------------------------- the GEMM
@@ -204,16 +205,16 @@ void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const u
     const u32x4_t *t = reinterpret_cast<const u32x4_t *>(tab);
     switch (BM) {
         case 32:
-            hipLaunchKernelGGL(toeplitz_gemm_kernel<32>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            GL_LAUNCH(toeplitz_gemm_kernel<32>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
             break;
         case 64:
-            hipLaunchKernelGGL(toeplitz_gemm_kernel<64>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            GL_LAUNCH(toeplitz_gemm_kernel<64>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
             break;
         case 128:
-            hipLaunchKernelGGL(toeplitz_gemm_kernel<128>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            GL_LAUNCH(toeplitz_gemm_kernel<128>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
             break;
         default:
-            hipLaunchKernelGGL(toeplitz_gemm_kernel<256>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            GL_LAUNCH(toeplitz_gemm_kernel<256>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
             break;
     }
 }
@@ -231,7 +232,7 @@ __global__ void old_reduce_kernel(const float *__restrict__ part, int nchunk, in
 void launch_old_reduce(const float *part, int nchunk, int64_t BM, int64_t P, double *old,
                        hipStream_t s) {
     const int64_t BP = BM * P;
-    hipLaunchKernelGGL(old_reduce_kernel, dim3((unsigned)((BP + 255) / 256)), dim3(256), 0, s, part,
+    GL_LAUNCH(old_reduce_kernel, dim3((unsigned)((BP + 255) / 256)), dim3(256), 0, s, part,
                        nchunk, BP, old);
 }
 
