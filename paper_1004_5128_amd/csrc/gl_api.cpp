@@ -26,6 +26,15 @@ struct gl_ctx {
     double *partial = nullptr;  // kMaxSplits x max P (FP64)
     int *d_flag = nullptr;
     float *tpart = nullptr;  // Toeplitz product chunks: max chunks x B x max P (FP32)
+    int64_t C = 500;         // adjoint recompute segment length (snapshot interval)
+    // adjoint work buffers, allocated on the first gl_adjoint call (sized for the largest problem)
+    float *adj_M = nullptr;      // reverse-time history of mu rows, max_steps x max ld
+    double *adj_u = nullptr;     // recomputed states of one segment, (C + 1) x max P
+    double *adj_S = nullptr;     // the forward sums S[k] of one segment, C x max P
+    double *adj_G = nullptr;     // the sums with d psi / d gamma, C x max P
+    double *adj_lam[2] = {nullptr, nullptr};
+    double *adj_grad = nullptr;  // per step and workgroup partial dot products, 3 each
+    int64_t maxP = 0, maxld = 0;
     int B = 256;             // block length of the Toeplitz path
     gl::Tuning tune;
     std::vector<void *> allocs;
@@ -171,6 +180,9 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
                 2 * (size_t)pb.P * sizeof(double);
         if (toep) need += 16 * (size_t)tab_len * sizeof(uint16_t) + (size_t)ctx->B * pb.P * sizeof(double);
     }
+    ctx->C = opt.ckpt_every > 0 ? opt.ckpt_every : 500;
+    const int64_t nsnap = opt.max_steps / ctx->C + 1;
+    for (const gl::Problem &pb : ctx->probs) need += (size_t)nsnap * pb.P * sizeof(double);
     need += (size_t)gl::kMaxSplits * maxP * sizeof(double);
     if (toep) need += (size_t)nchunk_max * ctx->B * maxP * sizeof(float);
     size_t free_b = 0, total_b = 0;
@@ -196,6 +208,9 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
         if ((st = dev_alloc(ctx, &pb.H, (size_t)rows * pb.ld))) return st;
         if ((st = dev_alloc(ctx, &pb.u[0], pb.P))) return st;
         if ((st = dev_alloc(ctx, &pb.u[1], pb.P))) return st;
+        if ((st = dev_alloc(ctx, &pb.snap, (size_t)nsnap * pb.P))) return st;
+        ctx->maxP = std::max(ctx->maxP, pb.P);
+        ctx->maxld = std::max(ctx->maxld, pb.ld);
         gl::launch_weights(pb.p.gamma, npsi - 1, pb.psi, pb.dpsi, ctx->stream);
         HIP_TRY(ctx, hipGetLastError());
         if (toep) {
@@ -275,6 +290,8 @@ gl_status load_initial(gl_ctx *ctx, const double *u0) {
         pb.old_k0 = -1;
         HIP_TRY(ctx, hipMemcpyAsync(pb.u[0], u0 + pb.offset, pb.P * sizeof(double),
                                     hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(pb.snap, u0 + pb.offset, pb.P * sizeof(double),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
     }
     ctx->k = 0;
     HIP_TRY(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));
@@ -283,6 +300,14 @@ gl_status load_initial(gl_ctx *ctx, const double *u0) {
     HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (flag) return fail(ctx, GL_ENONFINITE, "u0 holds NaN or Inf");
+    return GL_OK;
+}
+
+// After a step that reached k (multiple of C), keeps u[k] as the snapshot k / C.
+gl_status take_snapshot(gl_ctx *ctx, gl::Problem &pb, int64_t k) {
+    if (k % ctx->C == 0)
+        HIP_TRY(ctx, hipMemcpyAsync(pb.snap + (k / ctx->C) * pb.P, pb.u[pb.cur],
+                                    pb.P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     return GL_OK;
 }
 
@@ -307,11 +332,12 @@ gl_status step_gemv(gl_ctx *ctx) {
             if (st != GL_OK) return st;
         }
         st = timed(ctx, GL_KERNEL_UPDATE, [&] {
-            gl::launch_update(pb, u, nullptr, un, pb.H + k * pb.ld, ctx->partial, nsplit,
+            gl::launch_update(pb, u, nullptr, un, pb.H + k * pb.ld, nullptr, ctx->partial, nsplit,
                               ctx->stream);
         });
         if (st != GL_OK) return st;
         pb.cur ^= 1;
+        if ((st = take_snapshot(ctx, pb, k + 1)) != GL_OK) return st;
     }
     HIP_TRY(ctx, hipGetLastError());
     ctx->k = k + 1;
@@ -332,42 +358,156 @@ gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld,
     });
 }
 
+// Step k -> k + 1 of one problem on the blocked path, from u_cur into u_next (S_out,
+// nullable, receives the step's sum; write_history 0 leaves history row k alone).
+gl_status toeplitz_step_one(gl_ctx *ctx, gl::Problem &pb, int64_t k, const double *u_cur,
+                            double *u_next, double *S_out, int write_history) {
+    const int64_t b = k % ctx->B;
+    const int64_t k0 = k - b;
+    gl_status st;
+    if (k0 > 0 && pb.old_k0 != k0) {
+        if ((st = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old)) != GL_OK) return st;
+        pb.old_k0 = k0;
+    }
+    gl::BlockStepArgs args{};
+    args.psi = pb.psi;
+    args.H = pb.H;
+    args.ld = pb.ld;
+    args.P = pb.P;
+    args.ndim = pb.p.ndim;
+    args.nx = pb.p.nx;
+    args.ny = pb.p.ny;
+    args.rxn = pb.p.rxn;
+    args.r = pb.r;
+    args.dt = pb.p.dt;
+    args.rate = pb.p.rxn_rate;
+    args.old = k0 > 0 ? pb.old : nullptr;
+    args.u_cur = u_cur;
+    args.u_next = u_next;
+    args.S_out = S_out;
+    args.k0 = k0;
+    args.b = (int32_t)b;
+    args.write_history = write_history;
+    return timed(ctx, GL_KERNEL_TRIANGLE, [&] { gl::launch_block_step(args, ctx->stream); });
+}
+
 // One step k -> k + 1 on the blocked path: at the start of each block of B steps the
 // sums over the states before the block are formed by the Toeplitz product; each step is
 // then one kernel (rows inside the block, stencil, update).
 gl_status step_toeplitz(gl_ctx *ctx) {
     const int64_t k = ctx->k;
-    const int64_t b = k % ctx->B;
-    const int64_t k0 = k - b;
     for (gl::Problem &pb : ctx->probs) {
-        gl_status st;
-        if (k0 > 0 && pb.old_k0 != k0) {
-            if ((st = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old)) != GL_OK) return st;
-            pb.old_k0 = k0;
-        }
-        gl::BlockStepArgs args{};
-        args.psi = pb.psi;
-        args.H = pb.H;
-        args.ld = pb.ld;
-        args.P = pb.P;
-        args.ndim = pb.p.ndim;
-        args.nx = pb.p.nx;
-        args.ny = pb.p.ny;
-        args.rxn = pb.p.rxn;
-        args.r = pb.r;
-        args.dt = pb.p.dt;
-        args.rate = pb.p.rxn_rate;
-        args.old = k0 > 0 ? pb.old : nullptr;
-        args.u_cur = pb.u[pb.cur];
-        args.u_next = pb.u[pb.cur ^ 1];
-        args.k0 = k0;
-        args.b = (int32_t)b;
-        st = timed(ctx, GL_KERNEL_TRIANGLE, [&] { gl::launch_block_step(args, ctx->stream); });
+        gl_status st = toeplitz_step_one(ctx, pb, k, pb.u[pb.cur], pb.u[pb.cur ^ 1], nullptr, 1);
         if (st != GL_OK) return st;
         pb.cur ^= 1;
+        if ((st = take_snapshot(ctx, pb, k + 1)) != GL_OK) return st;
     }
     HIP_TRY(ctx, hipGetLastError());
     ctx->k = k + 1;
+    return GL_OK;
+}
+
+// Recomputes u[ks..ke] of one problem from the snapshot u[ks] with the forward's own
+// kernels (bit-identical to the forward run), keeping u[k] in adj_u, the step sums S[k]
+// in adj_S and the sums G[k] with d psi / d gamma in adj_G (k in [ks, ke)).
+gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke) {
+    const int64_t P = pb.P;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_u, pb.snap + (ks / ctx->C) * P, P * sizeof(double),
+                                hipMemcpyDeviceToDevice, ctx->stream));
+    const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
+    for (int64_t k = ks; k < ke; ++k) {
+        const int64_t i = k - ks;
+        const double *u = ctx->adj_u + i * P;
+        double *un = ctx->adj_u + (i + 1) * P;
+        double *S = ctx->adj_S + i * P;
+        const int64_t rb = ctx->sched.run_begin[k];
+        const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
+        const int64_t T = ctx->sched.terms[k];
+        const int nsplit = gl::gemv_splits(T - 1, P, ctx->tune.gemv_groups);
+        gl_status st;
+        if (toep) {
+            if ((st = toeplitz_step_one(ctx, pb, k, u, un, S, 0)) != GL_OK) return st;
+        } else {
+            const bool reverse = ctx->tune.serpentine && (k & 1);
+            if (nsplit > 0)
+                gl::launch_hist_gemv(pb.H, pb.ld, P, pb.psi, ctx->d_runs + rb, nruns, k, 1, T,
+                                     nsplit, reverse, ctx->partial, ctx->stream);
+            gl::launch_update(pb, u, nullptr, un, nullptr, S, ctx->partial, nsplit, ctx->stream);
+        }
+        // G[k] = sum over the same terms of d psi / d gamma (m) delta[k-m]; the m = 0 weight is 0
+        if (nsplit > 0)
+            gl::launch_hist_gemv(pb.H, pb.ld, P, pb.dpsi, ctx->d_runs + rb, nruns, k, 1, T, nsplit,
+                                 false, ctx->partial, ctx->stream);
+        gl::launch_reduce_partials(ctx->partial, nsplit, P, nullptr, ctx->adj_G + i * P,
+                                   ctx->stream);
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    return GL_OK;
+}
+
+gl_status adjoint_alloc(gl_ctx *ctx) {
+    if (ctx->adj_M) return GL_OK;
+    const int64_t C = ctx->C, n = ctx->opt.max_steps;
+    const int groups = gl::adjoint_groups(ctx->maxP);
+    const size_t need = ((size_t)n * ctx->maxld) * sizeof(float) +
+                        ((size_t)(3 * C + 1) * ctx->maxP + 2 * (size_t)ctx->maxP +
+                         (size_t)n * groups * 3) * sizeof(double);
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
+    if (need + (size_t)(256u << 20) > free_b)
+        return fail(ctx, GL_ENOMEM, "gl_adjoint: need %.3f GB of device memory, %.3f GB free",
+                    need / 1e9, free_b / 1e9);
+    gl_status st;
+    if ((st = dev_alloc(ctx, &ctx->adj_M, (size_t)n * ctx->maxld))) return st;
+    if ((st = dev_alloc(ctx, &ctx->adj_u, (size_t)(C + 1) * ctx->maxP))) return st;
+    if ((st = dev_alloc(ctx, &ctx->adj_S, (size_t)C * ctx->maxP))) return st;
+    if ((st = dev_alloc(ctx, &ctx->adj_G, (size_t)C * ctx->maxP))) return st;
+    if ((st = dev_alloc(ctx, &ctx->adj_lam[0], ctx->maxP))) return st;
+    if ((st = dev_alloc(ctx, &ctx->adj_lam[1], ctx->maxP))) return st;
+    if ((st = dev_alloc(ctx, &ctx->adj_grad, (size_t)n * groups * 3))) return st;
+    return GL_OK;
+}
+
+// Reverse sweep of every problem over the steps taken so far (see gl_adjoint.hip).
+gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *dparams) {
+    gl_status st;
+    if ((st = adjoint_alloc(ctx)) != GL_OK) return st;
+    const int64_t n = ctx->k, C = ctx->C;
+    for (size_t ip = 0; ip < ctx->probs.size(); ++ip) {
+        gl::Problem &pb = ctx->probs[ip];
+        const int64_t P = pb.P;
+        const int groups = gl::adjoint_groups(P);
+        int cur = 0;
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_lam[0], dL_duT + pb.offset, P * sizeof(double),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        for (int64_t seg = (n - 1) / C; seg >= 0; --seg) {
+            const int64_t ks = seg * C, ke = std::min(ks + C, n);
+            if ((st = adjoint_recompute(ctx, pb, ks, ke)) != GL_OK) return st;
+            for (int64_t k = ke - 1; k >= ks; --k) {
+                const int64_t rho = n - 1 - k;  // reverse step: the forward schedule at rho
+                const int64_t rb = ctx->sched.run_begin[rho];
+                const int nruns = (int)(ctx->sched.run_begin[rho + 1] - rb);
+                const int64_t T = ctx->sched.terms[rho];
+                const int nsplit = gl::gemv_splits(T - 1, P, ctx->tune.gemv_groups);
+                if (nsplit > 0)
+                    gl::launch_hist_gemv(ctx->adj_M, pb.ld, P, pb.psi, ctx->d_runs + rb, nruns, rho,
+                                         1, T, nsplit, false, ctx->partial, ctx->stream);
+                const int64_t i = k - ks;
+                gl::launch_adjoint_update(pb, ctx->adj_lam[cur], ctx->adj_lam[cur ^ 1],
+                                          ctx->adj_M + rho * pb.ld, ctx->partial, nsplit,
+                                          ctx->adj_u + i * P, ctx->adj_S + i * P,
+                                          ctx->adj_G + i * P, ctx->adj_grad + k * groups * 3,
+                                          ctx->stream);
+                cur ^= 1;
+            }
+            HIP_TRY(ctx, hipGetLastError());
+        }
+        HIP_TRY(ctx, hipMemcpyAsync(dL_du0 + pb.offset, ctx->adj_lam[cur], P * sizeof(double),
+                                    hipMemcpyDeviceToDevice, ctx->stream));
+        gl::launch_adjoint_final(ctx->adj_grad, n * groups, pb.r, pb.p.alpha, std::log(pb.p.dt),
+                                 pb.p.dt, dparams + 3 * ip, ctx->stream);
+        HIP_TRY(ctx, hipGetLastError());
+    }
     return GL_OK;
 }
 
@@ -462,7 +602,15 @@ gl_status gl_adjoint(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *
     if (!ctx) return fail(nullptr, GL_EINVAL, "gl_adjoint: ctx is NULL");
     if (!dL_duT || !dL_du0 || !dparams) return fail(ctx, GL_EINVAL, "gl_adjoint: NULL argument");
     if (ctx->k < 1) return fail(ctx, GL_ESTATE, "gl_adjoint: no forward step taken");
-    return fail(ctx, GL_EUNSUPPORTED, "gl_adjoint: not built yet");
+    if (ctx->opt.mem_mode == GL_MEM_ADAPTIVE)
+        return fail(ctx, GL_EUNSUPPORTED,
+                    "gl_adjoint: the adaptive schedule's transpose is not built (full or short "
+                    "memory only)");
+    gl_status st = adjoint_impl(ctx, dL_duT, dL_du0, dparams);
+    for (gl::Problem &pb : ctx->probs) pb.old_k0 = -1;  // block sums were reused as scratch
+    if (st != GL_OK) return st;
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    return resolve_profile(ctx);
 }
 
 void gl_free(gl_ctx *ctx) {

@@ -100,7 +100,8 @@ __global__ __launch_bounds__(kStepThreads) void block_step_kernel(BlockStepArgs 
     for (int g = 0; g < kStepGroups; ++g) S += red[g][tid];
     const double uk = u[q];
     a.u_next[q] = uk + a.dt * step_reaction(a.rxn, a.rate, uk) + a.r * S;
-    a.H[k * a.ld + q] = (float)d;
+    if (a.write_history) a.H[k * a.ld + q] = (float)d;
+    if (a.S_out) a.S_out[q] = S;
 }
 
 void launch_block_step(const BlockStepArgs &args, hipStream_t s) {

@@ -70,6 +70,8 @@ struct Problem {
     int64_t tab_len = 0;
     double *old = nullptr;        // [B x P] FP64 sums over the states before the current block
     int64_t old_k0 = -1;          // block start old[] belongs to (-1: none)
+    // adjoint: FP64 snapshots of u every C steps, snap[i] = u[i C]
+    double *snap = nullptr;
 };
 
 // ---------------------------------------------------------------- kernels
@@ -130,8 +132,10 @@ struct BlockStepArgs {
     const double *old;  // [B x P] sums over the states before the block, or nullptr (k0 = 0)
     const double *u_cur;
     double *u_next;
+    double *S_out;          // nullable: receives the step's full sum S
     int64_t k0;
     int32_t b;
+    int32_t write_history;  // 0: leave history row k untouched (recomputation)
 };
 
 // One in-block step as a single kernel (history sum over rows k0..k-1, stencil,
@@ -143,9 +147,23 @@ void launch_reduce_partials(const double *partial, int nsplit, int64_t P, const 
                             double *S, hipStream_t s);
 
 // One explicit step after the GEMV: d = stencil(u); S = d (+ base) + sum_s partial[s];
-// unew = u + dt f(u) + r S; Hk (history row k) = (float) d.
+// unew = u + dt f(u) + r S; Hk (history row k, nullable) = (float) d; S_out (nullable) = S.
 void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
-                   float *Hk, const double *partial, int nsplit, hipStream_t s);
+                   float *Hk, double *S_out, const double *partial, int nsplit, hipStream_t s);
+
+// ---- adjoint
+// One reverse step: mu = r stencil(lam1); A = mu + sum_s partial[s];
+// lam0 = lam1 + dt f'(uk) lam1 + A; Mrow = (float) mu; and per-workgroup partial sums
+// of lam1 * Sk, lam1 * Gk, lam1 * df/drate(uk) into grad[3 * blockIdx].
+void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, float *Mrow,
+                           const double *partial, int nsplit, const double *uk, const double *Sk,
+                           const double *Gk, double *grad, hipStream_t s);
+// Workgroups of one adjoint update launch for P points.
+int adjoint_groups(int64_t P);
+// dparams[0..2] = {dL/dalpha, dL/dgamma, dL/drate} from the per-step partial sums
+// grad[n * 3] (n entries in the fixed order they were written).
+void launch_adjoint_final(const double *grad, int64_t n, double r, double alpha, double lndt,
+                          double dt, double *dparams, hipStream_t s);
 
 // *flag = 1 if any of x[0..n) is NaN or Inf (flag must start at 0).
 void launch_check_finite(const double *x, int64_t n, int *flag, hipStream_t s);

@@ -197,8 +197,8 @@ __device__ __forceinline__ double stencil_at(const double *__restrict__ u, int64
 
 __global__ __launch_bounds__(256) void update_kernel(
     const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
-    float *__restrict__ Hk, const double *__restrict__ partial, int nsplit, int64_t P, int ndim,
-    int nx, int ny, double r, double dt, int rxn, double rate) {
+    float *__restrict__ Hk, double *__restrict__ S_out, const double *__restrict__ partial,
+    int nsplit, int64_t P, int ndim, int nx, int ny, double r, double dt, int rxn, double rate) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const double d = stencil_at(u, p, ndim, nx, ny);
@@ -215,15 +215,15 @@ __global__ __launch_bounds__(256) void update_kernel(
     for (; q < nsplit; ++q) s += partial[(int64_t)q * P + p];
     const double uk = u[p];
     unew[p] = uk + dt * reaction(rxn, rate, uk) + r * s;
-    Hk[p] = (float)d;
+    if (Hk) Hk[p] = (float)d;
+    if (S_out) S_out[p] = s;
 }
 
 void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
-                   float *Hk, const double *partial, int nsplit, hipStream_t s) {
+                   float *Hk, double *S_out, const double *partial, int nsplit, hipStream_t s) {
     const gl_problem &p = pb.p;
-    GL_LAUNCH(update_kernel, dim3((unsigned)((pb.P + 255) / 256)), dim3(256), 0, s, u,
-                       base, unew, Hk, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, pb.r, p.dt,
-                       p.rxn, p.rxn_rate);
+    GL_LAUNCH(update_kernel, dim3((unsigned)((pb.P + 255) / 256)), dim3(256), 0, s, u, base, unew,
+              Hk, S_out, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, pb.r, p.dt, p.rxn, p.rxn_rate);
 }
 
 // ----------------------------------------------------------------- helpers
