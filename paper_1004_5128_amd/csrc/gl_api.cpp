@@ -26,6 +26,9 @@ struct gl_ctx {
     double *partial = nullptr;  // kMaxSplits x max P (FP64)
     int *d_flag = nullptr;
     float *tpart = nullptr;  // Toeplitz product chunks: max chunks x B x max P (FP32)
+    gl::BatchEntry *d_batch = nullptr;  // one entry per problem (batched plain-path launches)
+    double *bpartial = nullptr;          // per-problem GEMV partial regions of the batch
+    int64_t upd_wgs = 0;                 // workgroups of one batched update launch
     int64_t C = 500;         // adjoint recompute segment length (snapshot interval)
     // adjoint work buffers, allocated on the first gl_adjoint call (sized for the largest problem)
     float *adj_M = nullptr;      // reverse-time history of mu rows, max_steps x max ld
@@ -183,7 +186,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     ctx->C = opt.ckpt_every > 0 ? opt.ckpt_every : 500;
     const int64_t nsnap = opt.max_steps / ctx->C + 1;
     for (const gl::Problem &pb : ctx->probs) need += (size_t)nsnap * pb.P * sizeof(double);
-    need += (size_t)gl::kMaxSplits * maxP * sizeof(double);
+    need += 2 * (size_t)gl::kMaxSplits * ctx->total_points * sizeof(double);  // partials (bound)
     if (toep) need += (size_t)nchunk_max * ctx->B * maxP * sizeof(float);
     size_t free_b = 0, total_b = 0;
     HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
@@ -192,7 +195,21 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
                     need / 1e9, free_b / 1e9);
 
     ctx->sched = gl::build_schedule(opt, opt.max_steps);
+    int64_t max_terms = 1;
+    for (int64_t t : ctx->sched.terms) max_terms = std::max(max_terms, t);
+    std::vector<int64_t> bsplits(nprob);
+    size_t bpart = 0;
+    for (int32_t i = 0; i < nprob; ++i) {
+        gl::Problem &pb = ctx->probs[i];
+        // an ensemble shares the workgroup target in proportion to the problems' sizes
+        pb.gemv_groups = std::max<int64_t>(
+            1, (ctx->tune.gemv_groups * pb.P + ctx->total_points - 1) / ctx->total_points);
+        bsplits[i] = std::max(1, gl::gemv_splits(max_terms - 1, pb.P, pb.gemv_groups));
+        bpart += (size_t)bsplits[i] * pb.P;
+    }
     gl_status st;
+    if ((st = dev_alloc(ctx, &ctx->bpartial, bpart))) return st;
+    if ((st = dev_alloc(ctx, &ctx->d_batch, (size_t)nprob))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_runs, ctx->sched.runs.size()))) return st;
     HIP_TRY(ctx, hipMemcpy(ctx->d_runs, ctx->sched.runs.data(),
                            ctx->sched.runs.size() * sizeof(gl::Run), hipMemcpyHostToDevice));
@@ -213,6 +230,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
         ctx->maxld = std::max(ctx->maxld, pb.ld);
         gl::launch_weights(pb.p.gamma, npsi - 1, pb.psi, pb.dpsi, ctx->stream);
         HIP_TRY(ctx, hipGetLastError());
+        ctx->upd_wgs += (pb.P + 255) / 256;
         if (toep) {
             pb.tab_len = tab_len;
             if ((st = dev_alloc(ctx, &pb.psi_tab, 16 * (size_t)tab_len))) return st;
@@ -221,6 +239,31 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
             HIP_TRY(ctx, hipGetLastError());
         }
     }
+    // device table of the problems for the batched launches
+    std::vector<gl::BatchEntry> tab(nprob);
+    size_t off = 0;
+    for (int32_t i = 0; i < nprob; ++i) {
+        const gl::Problem &pb = ctx->probs[i];
+        gl::BatchEntry &e = tab[i];
+        e.H = pb.H;
+        e.ld = pb.ld;
+        e.P = pb.P;
+        e.psi = pb.psi;
+        e.u[0] = pb.u[0];
+        e.u[1] = pb.u[1];
+        e.partial = ctx->bpartial + off;
+        e.groups = pb.gemv_groups;
+        off += (size_t)bsplits[i] * pb.P;
+        e.ndim = pb.p.ndim;
+        e.nx = pb.p.nx;
+        e.ny = pb.p.ny;
+        e.rxn = pb.p.rxn;
+        e.r = pb.r;
+        e.dt = pb.p.dt;
+        e.rate = pb.p.rxn_rate;
+    }
+    HIP_TRY(ctx, hipMemcpy(ctx->d_batch, tab.data(), tab.size() * sizeof(gl::BatchEntry),
+                           hipMemcpyHostToDevice));
     return load_initial(ctx, u0);
 }
 
@@ -311,31 +354,31 @@ gl_status take_snapshot(gl_ctx *ctx, gl::Problem &pb, int64_t k) {
     return GL_OK;
 }
 
-// One step k -> k + 1 of every problem on the plain GEMV path.
+// One step k -> k + 1 of every problem on the plain GEMV path: one batched GEMV launch
+// over all problems' history rows (terms m >= 1; psi(0) delta[k] is added in FP64 by
+// the update) and one batched update launch.
 gl_status step_gemv(gl_ctx *ctx) {
     const int64_t k = ctx->k;
     const int64_t rb = ctx->sched.run_begin[k];
     const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
     const int64_t T = ctx->sched.terms[k];
-    for (gl::Problem &pb : ctx->probs) {
-        const double *u = pb.u[pb.cur];
-        double *un = pb.u[pb.cur ^ 1];
-        // term 0 is (m = 0, coef 1): psi(0) u[k] = u[k] comes from the FP64 state
-        const int nsplit = gl::gemv_splits(T - 1, pb.P, ctx->tune.gemv_groups);
-        const bool reverse = ctx->tune.serpentine && (k & 1);
-        gl_status st;
-        if (nsplit > 0) {
-            st = timed(ctx, GL_KERNEL_HIST_GEMV, [&] {
-                gl::launch_hist_gemv(pb.H, pb.ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 1, T,
-                                     nsplit, reverse, ctx->partial, ctx->stream);
-            });
-            if (st != GL_OK) return st;
-        }
-        st = timed(ctx, GL_KERNEL_UPDATE, [&] {
-            gl::launch_update(pb, u, nullptr, un, pb.H + k * pb.ld, nullptr, ctx->partial, nsplit,
-                              ctx->stream);
+    const int nprob = (int)ctx->probs.size();
+    const int cur = ctx->probs[0].cur;
+    const bool reverse = ctx->tune.serpentine && (k & 1);
+    const int64_t wgs = gl::batched_gemv_groups(ctx->probs, T - 1);
+    gl_status st;
+    if (wgs > 0) {
+        st = timed(ctx, GL_KERNEL_HIST_GEMV, [&] {
+            gl::launch_hist_gemv_batched(ctx->d_batch, nprob, wgs, ctx->d_runs + rb, nruns, k, 1, T,
+                                         reverse, ctx->stream);
         });
         if (st != GL_OK) return st;
+    }
+    st = timed(ctx, GL_KERNEL_UPDATE, [&] {
+        gl::launch_update_batched(ctx->d_batch, nprob, ctx->upd_wgs, k, cur, T - 1, ctx->stream);
+    });
+    if (st != GL_OK) return st;
+    for (gl::Problem &pb : ctx->probs) {
         pb.cur ^= 1;
         if ((st = take_snapshot(ctx, pb, k + 1)) != GL_OK) return st;
     }
@@ -423,7 +466,7 @@ gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke
         const int64_t rb = ctx->sched.run_begin[k];
         const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
         const int64_t T = ctx->sched.terms[k];
-        const int nsplit = gl::gemv_splits(T - 1, P, ctx->tune.gemv_groups);
+        const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
         gl_status st;
         if (toep) {
             if ((st = toeplitz_step_one(ctx, pb, k, u, un, S, 0)) != GL_OK) return st;
@@ -488,7 +531,7 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
                 const int64_t rb = ctx->sched.run_begin[rho];
                 const int nruns = (int)(ctx->sched.run_begin[rho + 1] - rb);
                 const int64_t T = ctx->sched.terms[rho];
-                const int nsplit = gl::gemv_splits(T - 1, P, ctx->tune.gemv_groups);
+                const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
                 if (nsplit > 0)
                     gl::launch_hist_gemv(ctx->adj_M, pb.ld, P, pb.psi, ctx->d_runs + rb, nruns, rho,
                                          1, T, nsplit, false, ctx->partial, ctx->stream);

@@ -72,6 +72,9 @@ struct Problem {
     int64_t old_k0 = -1;          // block start old[] belongs to (-1: none)
     // adjoint: FP64 snapshots of u every C steps, snap[i] = u[i C]
     double *snap = nullptr;
+    // workgroup target of this problem's history GEMV: the context's target, shared among
+    // the problems of an ensemble in proportion to their sizes
+    int64_t gemv_groups = 1024;
 };
 
 // ---------------------------------------------------------------- kernels
@@ -84,7 +87,7 @@ constexpr int kGemvCols = 1024;
 
 // Number of row splits of the history GEMV for `terms` terms over P points,
 // aiming at about target_groups workgroups.
-int gemv_splits(int64_t terms, int64_t P, int64_t target_groups);
+__host__ __device__ int gemv_splits(int64_t terms, int64_t P, int64_t target_groups);
 constexpr int kMaxSplits = 64;
 
 // partial[s * P + p] = sum over terms t in split s of [t_begin, t_end) of the
@@ -93,6 +96,30 @@ constexpr int kMaxSplits = 64;
 void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, const Run *runs,
                       int nruns, int64_t k, int64_t t_begin, int64_t t_end, int nsplit,
                       bool reverse, double *partial, hipStream_t s);
+
+// One problem of a batched (ensemble) launch; a device-resident table, one entry per
+// problem, built at gl_init.
+struct BatchEntry {
+    float *H;
+    int64_t ld, P;
+    const double *psi;
+    double *u[2];
+    double *partial;  // this problem's GEMV partials, up to its split count x P
+    int64_t groups;   // this problem's GEMV workgroup target (Problem::gemv_groups)
+    int32_t ndim, nx, ny, rxn;
+    double r, dt, rate;
+};
+
+// Workgroups of one batched GEMV launch over every problem for `terms` terms.
+int64_t batched_gemv_groups(const std::vector<Problem> &probs, int64_t terms);
+// One launch: for every problem, partial[s * P + p] of terms [t_begin, t_end) at step k.
+void launch_hist_gemv_batched(const BatchEntry *tab, int nprob, int64_t wgs, const Run *runs,
+                              int nruns, int64_t k, int64_t t_begin, int64_t t_end, bool reverse,
+                              hipStream_t s);
+// One launch: the update of every problem from u[cur] into u[cur ^ 1], history row k;
+// `terms` = the GEMV's term count (t_end - t_begin), for each problem's split count.
+void launch_update_batched(const BatchEntry *tab, int nprob, int64_t wgs, int64_t k, int cur,
+                           int64_t terms, hipStream_t s);
 
 // Tuning (defaults; GL_GEMV_GROUPS, GL_GEMV_SERPENTINE and GL_TOEPLITZ_KCHUNK in
 // the environment override them at gl_init).

@@ -4,6 +4,14 @@
 
 #include "gl_internal.h"
 
+// Address spaces of device pointers: global memory, and constant (read-only) memory
+// whose wave-uniform loads go through the scalar unit.  The kernels shared by the single
+// and batched launches take qualified pointers, because pointers read from a table in
+// memory would otherwise become generic (flat) accesses.
+#define GL_GLOBAL __attribute__((address_space(1)))
+#define GL_CONST __attribute__((address_space(4)))
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
 namespace gl {
 
 // ------------------------------------------------------------------ weights
@@ -49,91 +57,113 @@ void launch_weights(double gamma, int64_t n, double *psi, double *dpsi, hipStrea
 constexpr int kGemvThreads = 256;
 constexpr int kGemvUnroll = 8;
 
+// Terms [ta, tb) of the step-k schedule for the four points col..col+3 (col < P):
+// returns their FP64 sums in a[0..3].
+__device__ __forceinline__ void gemv_points(const GL_GLOBAL float *__restrict__ H, int64_t ld,
+                                            const GL_CONST double *__restrict__ psi,
+                                            const GL_CONST Run *__restrict__ runs, int nruns,
+                                            int64_t k, int64_t ta, int64_t tb, int64_t col,
+                                            int reverse, double a[4]) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    // Runs are visited in order; with `reverse` the terms are walked from the last to the
+    // first (oldest row first), so that consecutive steps can traverse the history in
+    // opposite directions.
+    int64_t tr0 = 0;
+    if (reverse)
+        for (int r = 0; r < nruns; ++r) tr0 += runs[r].count;
+    for (int rr = 0; rr < nruns; ++rr) {
+        const int r = reverse ? nruns - 1 - rr : rr;
+        const Run run = {runs[r].m0, runs[r].count, runs[r].stride, runs[r].coef};
+        int64_t tr1;
+        if (reverse) {
+            tr1 = tr0;
+            tr0 = tr1 - run.count;
+            if (tr1 <= ta) break;
+        } else {
+            tr1 = tr0 + run.count;
+            if (tr0 >= tb) break;
+        }
+        const int64_t lo = ta > tr0 ? ta : tr0;
+        const int64_t hi = tb < tr1 ? tb : tr1;
+        if (lo < hi) {
+            const int64_t stride = reverse ? -(int64_t)run.stride : (int64_t)run.stride;
+            const double coef = (double)run.coef;
+            int64_t m = run.m0 + ((reverse ? hi - 1 : lo) - tr0) * (int64_t)run.stride;
+            const GL_GLOBAL float *row = H + (k - m) * ld + col;
+            const int64_t step = stride * ld;
+            int64_t cnt = hi - lo;
+            while (cnt >= kGemvUnroll) {
+                f32x4_t v[kGemvUnroll];
+                double w[kGemvUnroll];
+#pragma unroll
+                for (int u = 0; u < kGemvUnroll; ++u)
+                    v[u] = *reinterpret_cast<const GL_GLOBAL f32x4_t *>(row - u * step);
+#pragma unroll
+                for (int u = 0; u < kGemvUnroll; ++u) w[u] = coef * psi[m + u * stride];
+#pragma unroll
+                for (int u = 0; u < kGemvUnroll; ++u) {
+                    a0 = fma(w[u], (double)v[u].x, a0);
+                    a1 = fma(w[u], (double)v[u].y, a1);
+                    a2 = fma(w[u], (double)v[u].z, a2);
+                    a3 = fma(w[u], (double)v[u].w, a3);
+                }
+                row -= kGemvUnroll * step;
+                m += kGemvUnroll * stride;
+                cnt -= kGemvUnroll;
+            }
+            for (; cnt > 0; --cnt) {
+                const f32x4_t v = *reinterpret_cast<const GL_GLOBAL f32x4_t *>(row);
+                const double w = coef * psi[m];
+                a0 = fma(w, (double)v.x, a0);
+                a1 = fma(w, (double)v.y, a1);
+                a2 = fma(w, (double)v.z, a2);
+                a3 = fma(w, (double)v.w, a3);
+                row -= step;
+                m += stride;
+            }
+        }
+        if (!reverse) tr0 = tr1;
+    }
+    a[0] = a0;
+    a[1] = a1;
+    a[2] = a2;
+    a[3] = a3;
+}
+
+// Split s of nsplit covers terms [t_begin + T s / nsplit, t_begin + T (s+1) / nsplit).
+__device__ __forceinline__ void gemv_split_range(int64_t t_begin, int64_t t_end, int split,
+                                                 int nsplit, int64_t *ta, int64_t *tb) {
+    const int64_t T = t_end - t_begin;
+    *ta = t_begin + (T * split) / nsplit;
+    *tb = t_begin + (T * (split + 1)) / nsplit;
+}
+
+__device__ __forceinline__ void store4(GL_GLOBAL double *out, int64_t col, int64_t P,
+                                       const double a[4]) {
+    out[0] = a[0];
+    if (col + 1 < P) out[1] = a[1];
+    if (col + 2 < P) out[2] = a[2];
+    if (col + 3 < P) out[3] = a[3];
+}
+
 __global__ __launch_bounds__(kGemvThreads) void hist_gemv_kernel(
     const float *__restrict__ H, int64_t ld, int64_t P, const double *__restrict__ psi,
     const Run *__restrict__ runs, int nruns, int64_t k, int64_t t_begin, int64_t t_end,
     int reverse, double *__restrict__ partial) {
-    const int nsplit = gridDim.y;
-    const int split = blockIdx.y;
-    const int64_t T = t_end - t_begin;
-    const int64_t ta = t_begin + (T * split) / nsplit;
-    const int64_t tb = t_begin + (T * (split + 1)) / nsplit;
     const int64_t col = ((int64_t)blockIdx.x * kGemvThreads + threadIdx.x) * 4;
-
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    if (col < P) {
-        // Runs are visited in order; with `reverse` each split walks its terms from the
-        // last to the first (oldest row first), so that consecutive steps traverse the
-        // history in opposite directions and the rows one step read last are still in
-        // the last-level cache when the next step starts.
-        int64_t tr0 = 0;
-        if (reverse)
-            for (int r = 0; r < nruns; ++r) tr0 += runs[r].count;
-        for (int rr = 0; rr < nruns; ++rr) {
-            const int r = reverse ? nruns - 1 - rr : rr;
-            const Run run = runs[r];
-            int64_t tr1;
-            if (reverse) {
-                tr1 = tr0;
-                tr0 = tr1 - run.count;
-                if (tr1 <= ta) break;
-            } else {
-                tr1 = tr0 + run.count;
-                if (tr0 >= tb) break;
-            }
-            const int64_t lo = ta > tr0 ? ta : tr0;
-            const int64_t hi = tb < tr1 ? tb : tr1;
-            if (lo < hi) {
-                const int64_t stride = reverse ? -(int64_t)run.stride : (int64_t)run.stride;
-                const double coef = (double)run.coef;
-                int64_t m = run.m0 + ((reverse ? hi - 1 : lo) - tr0) * (int64_t)run.stride;
-                const float *row = H + (k - m) * ld + col;
-                const int64_t step = stride * ld;
-                int64_t cnt = hi - lo;
-                while (cnt >= kGemvUnroll) {
-                    float4 v[kGemvUnroll];
-                    double w[kGemvUnroll];
-#pragma unroll
-                    for (int u = 0; u < kGemvUnroll; ++u)
-                        v[u] = *reinterpret_cast<const float4 *>(row - u * step);
-#pragma unroll
-                    for (int u = 0; u < kGemvUnroll; ++u) w[u] = coef * psi[m + u * stride];
-#pragma unroll
-                    for (int u = 0; u < kGemvUnroll; ++u) {
-                        a0 = fma(w[u], (double)v[u].x, a0);
-                        a1 = fma(w[u], (double)v[u].y, a1);
-                        a2 = fma(w[u], (double)v[u].z, a2);
-                        a3 = fma(w[u], (double)v[u].w, a3);
-                    }
-                    row -= kGemvUnroll * step;
-                    m += kGemvUnroll * stride;
-                    cnt -= kGemvUnroll;
-                }
-                for (; cnt > 0; --cnt) {
-                    const float4 v = *reinterpret_cast<const float4 *>(row);
-                    const double w = coef * psi[m];
-                    a0 = fma(w, (double)v.x, a0);
-                    a1 = fma(w, (double)v.y, a1);
-                    a2 = fma(w, (double)v.z, a2);
-                    a3 = fma(w, (double)v.w, a3);
-                    row -= step;
-                    m += stride;
-                }
-            }
-            if (!reverse) tr0 = tr1;
-        }
-        double *out = partial + (int64_t)split * P + col;
-        out[0] = a0;
-        if (col + 1 < P) out[1] = a1;
-        if (col + 2 < P) out[2] = a2;
-        if (col + 3 < P) out[3] = a3;
-    }
+    if (col >= P) return;
+    int64_t ta, tb;
+    gemv_split_range(t_begin, t_end, blockIdx.y, gridDim.y, &ta, &tb);
+    double a[4];
+    gemv_points((const GL_GLOBAL float *)H, ld, (const GL_CONST double *)psi,
+                (const GL_CONST Run *)runs, nruns, k, ta, tb, col, reverse, a);
+    store4((GL_GLOBAL double *)partial + (int64_t)blockIdx.y * P + col, col, P, a);
 }
 
-int gemv_splits(int64_t terms, int64_t P, int64_t target_groups) {
+__host__ __device__ int gemv_splits(int64_t terms, int64_t P, int64_t target_groups) {
     if (terms <= 0) return 0;
     const int64_t colblocks = (P + kGemvCols - 1) / kGemvCols;
-    // aim at target_groups workgroups (default ~8 per CU on 256 CUs), >= 16 terms per split
+    // aim at target_groups workgroups (default ~4 per CU on 256 CUs), >= 16 terms per split
     int64_t want = (target_groups + colblocks - 1) / colblocks;
     const int64_t by_terms = (terms + 15) / 16;
     if (want > by_terms) want = by_terms;
@@ -146,8 +176,53 @@ void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, 
                       int nruns, int64_t k, int64_t t_begin, int64_t t_end, int nsplit,
                       bool reverse, double *partial, hipStream_t s) {
     const unsigned colblocks = (unsigned)((P + kGemvCols - 1) / kGemvCols);
-    GL_LAUNCH(hist_gemv_kernel, dim3(colblocks, (unsigned)nsplit), dim3(kGemvThreads), 0,
-                       s, H, ld, P, psi, runs, nruns, k, t_begin, t_end, reverse ? 1 : 0, partial);
+    GL_LAUNCH(hist_gemv_kernel, dim3(colblocks, (unsigned)nsplit), dim3(kGemvThreads), 0, s, H, ld,
+              P, psi, runs, nruns, k, t_begin, t_end, reverse ? 1 : 0, partial);
+}
+
+// ---- batched over the problems of an ensemble: one launch for every problem's GEMV.
+// Workgroups are laid out problem after problem, each problem's share being
+// colblocks x nsplit with nsplit from the same rule as a single problem, so every
+// member's sums are bit-identical to its solo run.
+__global__ __launch_bounds__(kGemvThreads) void hist_gemv_batched_kernel(
+    const BatchEntry *__restrict__ tab, int nprob, const Run *__restrict__ runs, int nruns,
+    int64_t k, int64_t t_begin, int64_t t_end, int reverse) {
+    int64_t w = blockIdx.x;
+    int i = 0, nsplit = 0;
+    int64_t cb = 1;
+    for (; i < nprob; ++i) {
+        cb = (tab[i].P + kGemvCols - 1) / kGemvCols;
+        nsplit = gemv_splits(t_end - t_begin, tab[i].P, tab[i].groups);
+        const int64_t share = cb * nsplit;
+        if (w < share) break;
+        w -= share;
+    }
+    if (i >= nprob) return;
+    const BatchEntry &e = tab[i];
+    const int split = (int)(w / cb);
+    const int64_t col = ((w % cb) * kGemvThreads + threadIdx.x) * 4;
+    if (col >= e.P) return;
+    int64_t ta, tb;
+    gemv_split_range(t_begin, t_end, split, nsplit, &ta, &tb);
+    double a[4];
+    gemv_points((const GL_GLOBAL float *)e.H, e.ld, (const GL_CONST double *)e.psi,
+                (const GL_CONST Run *)runs, nruns, k, ta, tb, col, reverse, a);
+    store4((GL_GLOBAL double *)e.partial + (int64_t)split * e.P + col, col, e.P, a);
+}
+
+int64_t batched_gemv_groups(const std::vector<Problem> &probs, int64_t terms) {
+    int64_t total = 0;
+    for (const Problem &pb : probs)
+        total += ((pb.P + kGemvCols - 1) / kGemvCols) * gemv_splits(terms, pb.P, pb.gemv_groups);
+    return total;
+}
+
+void launch_hist_gemv_batched(const BatchEntry *tab, int nprob, int64_t wgs, const Run *runs,
+                              int nruns, int64_t k, int64_t t_begin, int64_t t_end, bool reverse,
+                              hipStream_t s) {
+    if (wgs <= 0) return;
+    GL_LAUNCH(hist_gemv_batched_kernel, dim3((unsigned)wgs), dim3(kGemvThreads), 0, s, tab, nprob,
+              runs, nruns, k, t_begin, t_end, reverse ? 1 : 0);
 }
 
 __global__ void reduce_partials_kernel(const double *__restrict__ partial, int nsplit, int64_t P,
@@ -180,8 +255,8 @@ __device__ __forceinline__ double reaction(int rxn, double rate, double u) {
     return 0.0;
 }
 
-__device__ __forceinline__ double stencil_at(const double *__restrict__ u, int64_t p, int ndim,
-                                             int nx, int ny) {
+__device__ __forceinline__ double stencil_at(const GL_GLOBAL double *__restrict__ u, int64_t p,
+                                             int ndim, int nx, int ny) {
     if (ndim == 1) {
         const double e = p + 1 < nx ? u[p + 1] : 0.0;
         const double w = p > 0 ? u[p - 1] : 0.0;
@@ -195,12 +270,16 @@ __device__ __forceinline__ double stencil_at(const double *__restrict__ u, int64
     return e + w - 4.0 * u[p] + n + s;
 }
 
-__global__ __launch_bounds__(256) void update_kernel(
-    const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
-    float *__restrict__ Hk, double *__restrict__ S_out, const double *__restrict__ partial,
-    int nsplit, int64_t P, int ndim, int nx, int ny, double r, double dt, int rxn, double rate) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= P) return;
+// One point of the update; returns nothing, writes unew[p], Hk[p] (nullable), S_out[p]
+// (nullable).
+__device__ __forceinline__ void update_point(const GL_GLOBAL double *__restrict__ u,
+                                             const GL_GLOBAL double *__restrict__ base,
+                                             GL_GLOBAL double *__restrict__ unew,
+                                             GL_GLOBAL float *__restrict__ Hk,
+                                             GL_GLOBAL double *__restrict__ S_out,
+                                             const GL_GLOBAL double *__restrict__ partial,
+                                             int nsplit, int64_t P, int ndim, int nx, int ny,
+                                             double r, double dt, int rxn, double rate, int64_t p) {
     const double d = stencil_at(u, p, ndim, nx, ny);
     double s = d;
     if (base) s += base[p];
@@ -219,11 +298,49 @@ __global__ __launch_bounds__(256) void update_kernel(
     if (S_out) S_out[p] = s;
 }
 
+__global__ __launch_bounds__(256) void update_kernel(
+    const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
+    float *__restrict__ Hk, double *__restrict__ S_out, const double *__restrict__ partial,
+    int nsplit, int64_t P, int ndim, int nx, int ny, double r, double dt, int rxn, double rate) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    update_point((const GL_GLOBAL double *)u, (const GL_GLOBAL double *)base,
+                 (GL_GLOBAL double *)unew, (GL_GLOBAL float *)Hk, (GL_GLOBAL double *)S_out,
+                 (const GL_GLOBAL double *)partial, nsplit, P, ndim, nx, ny, r, dt, rxn, rate, p);
+}
+
 void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
                    float *Hk, double *S_out, const double *partial, int nsplit, hipStream_t s) {
     const gl_problem &p = pb.p;
     GL_LAUNCH(update_kernel, dim3((unsigned)((pb.P + 255) / 256)), dim3(256), 0, s, u, base, unew,
               Hk, S_out, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, pb.r, p.dt, p.rxn, p.rxn_rate);
+}
+
+// Batched update: workgroups laid out problem after problem, ceil(P / 256) each.
+__global__ __launch_bounds__(256) void update_batched_kernel(const BatchEntry *__restrict__ tab,
+                                                             int nprob, int64_t k, int cur,
+                                                             int64_t terms) {
+    int64_t w = blockIdx.x;
+    int i = 0;
+    for (; i < nprob; ++i) {
+        const int64_t share = (tab[i].P + 255) / 256;
+        if (w < share) break;
+        w -= share;
+    }
+    if (i >= nprob) return;
+    const BatchEntry &e = tab[i];
+    const int64_t p = w * 256 + threadIdx.x;
+    if (p >= e.P) return;
+    const int nsplit = gemv_splits(terms, e.P, e.groups);
+    update_point((const GL_GLOBAL double *)e.u[cur], nullptr, (GL_GLOBAL double *)e.u[cur ^ 1],
+                 (GL_GLOBAL float *)e.H + k * e.ld, nullptr, (const GL_GLOBAL double *)e.partial,
+                 nsplit, e.P, e.ndim, e.nx, e.ny, e.r, e.dt, e.rxn, e.rate, p);
+}
+
+void launch_update_batched(const BatchEntry *tab, int nprob, int64_t wgs, int64_t k, int cur,
+                           int64_t terms, hipStream_t s) {
+    GL_LAUNCH(update_batched_kernel, dim3((unsigned)wgs), dim3(256), 0, s, tab, nprob, k, cur,
+              terms);
 }
 
 // ----------------------------------------------------------------- helpers

@@ -1,4 +1,7 @@
 """Helpers shared by the GPU tests: run a workload through libgl and compare."""
+import contextlib
+import os
+
 import numpy as np
 import torch
 
@@ -25,3 +28,25 @@ def rel_l2(a, b):
 
 def print_case(*args):
     print("[case]", *args, flush=True)
+
+
+GEMV_GROUPS = 1024   # the library's default workgroup target of the history GEMV
+
+
+def member_groups(P, P_total, groups=GEMV_GROUPS):
+    """The GEMV workgroup target an ensemble gives a member of P points (its size share)."""
+    return max(1, (groups * P + P_total - 1) // P_total)
+
+
+@contextlib.contextmanager
+def gemv_groups(value):
+    """Run a solo problem with the split target an ensemble member gets (GL_GEMV_GROUPS)."""
+    old = os.environ.get("GL_GEMV_GROUPS")
+    os.environ["GL_GEMV_GROUPS"] = str(value)
+    try:
+        yield
+    finally:
+        if old is None:
+            del os.environ["GL_GEMV_GROUPS"]
+        else:
+            os.environ["GL_GEMV_GROUPS"] = old

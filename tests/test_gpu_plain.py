@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from paper_1004_5128_amd import workloads as W
-from gpu_util import gl, gpu_run, print_case, rel_l2
+from gpu_util import gemv_groups, gl, gpu_run, member_groups, print_case, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -121,9 +121,11 @@ def test_ensemble_members_equal_solo_runs():
     with G.Solver(probs, mem, torch.as_tensor(np.concatenate(u0s)), max_steps=n) as s:
         out = s.step(n).cpu().numpy()
     off = 0
+    total = sum(W.npoints(p) for p in probs)
     for p, u0 in zip(probs, u0s):
         P = W.npoints(p)
-        assert np.array_equal(out[off:off + P], gpu_run(p, mem, u0, n))
+        with gemv_groups(member_groups(P, total)):   # a solo run with the member's split target
+            assert np.array_equal(out[off:off + P], gpu_run(p, mem, u0, n))
         assert rel_l2(out[off:off + P], oracle.run(p, mem, u0, n)) <= TOL_PLAIN
         off += P
 
