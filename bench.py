@@ -131,24 +131,40 @@ def summarize_counters(fetch_csv, write_csv, work):
     return lines
 
 
+def sub_block(B):
+    """The library's sub-block length for block length B (GL_SUBBLOCK, default 32; 0: none)."""
+    B2 = int(os.environ.get("GL_SUBBLOCK", "32"))
+    return B2 if 0 < B2 < B and B % B2 == 0 else 0
+
+
 def algorithmic_work(path, P, n, B, terms):
     """Algorithmic work of each kernel over one solve of n steps (see the design notes):
      hist_gemv:  every history row of terms m >= 1 read once, 4 bytes per point
      update:     u[k] read, u[k+1] and the FP32 history row k written (20 bytes per point)
      toeplitz:   6 flops (three BF16 products) per (block row, history row, point); its HBM
                  side: history rows read once, FP32 chunk products written
-     triangle:   one in-block step: rows m = 1..b (4 bytes each), u read and written, history
-                 row written, the block sum read (8 bytes) after the first block
-     old_reduce: the FP32 chunk products read, the FP64 block sums written"""
+     triangle:   one in-block step: the sub-block's rows before the step (4 bytes each), u read
+                 and written, history row written, each block sum read (8 bytes) once present
+     subblock:   the product over a block's rows before a sub-block (as toeplitz)
+     old_reduce, sub_reduce: the FP32 chunk products read, the FP64 sums written"""
     work = {"hist_gemv": ("hbm", 4 * P * sum(t - 1 for t in terms)),
             "update": ("hbm", 20 * P * n)}
     if path == "toeplitz":
         blocks = range(B, n, B)
         work["toeplitz"] = ("mfma", 6 * B * P * sum(blocks))
         work["toeplitz_bytes"] = ("hbm", P * sum(4 * k0 + 4 * B * -(-k0 // 2048) for k0 in blocks))
-        work["triangle"] = ("hbm", P * sum(4 * (k % B) + 20 + (8 if k >= B else 0)
-                                           for k in range(n)))
+        B2 = sub_block(B)
+        inner = [(k % B) % B2 if B2 else k % B for k in range(n)]   # rows summed by the step
+        work["triangle"] = ("hbm", P * sum(4 * b2 + 20 + (8 if k >= B else 0) +
+                                           (8 if (k % B) - b2 > 0 else 0)
+                                           for k, b2 in zip(range(n), inner)))
         work["old_reduce"] = ("hbm", B * P * sum(4 * -(-k0 // 2048) + 8 for k0 in blocks))
+        if B2:
+            # sub-block products: rows k0 .. k1-1 for every sub-block start k1 > k0 (< n)
+            rows = [k1 % B for k1 in range(B2, n, B2) if k1 % B]
+            work["subblock"] = ("mfma", 6 * B2 * P * sum(rows))
+            work["subblock_bytes"] = ("hbm", P * sum(4 * r + 4 * B2 for r in rows))
+            work["sub_reduce"] = ("hbm", B2 * P * 12 * len(rows))
     return work
 
 
@@ -169,7 +185,6 @@ def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
         s.reset(u0)
         s.advance(n)
     torch.cuda.synchronize()
-    s.set_profiling(True)
     log(path, "timed", steps)
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -177,9 +192,16 @@ def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
         s.advance(n)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    uT = s.state().cpu().numpy()
+    # per-kernel durations: one more solve with HIP events stamped at each kernel's start
+    # and end (kernels launched one by one, so no graph replay in this solve)
+    log(path, "profiled solve")
+    s.set_profiling(True)
+    s.reset(u0)
+    s.advance(n)
+    torch.cuda.synchronize()
     prof = s.profile()
     s.set_profiling(False)
-    uT = s.state().cpu().numpy()
     u_prefix = None
     if prefix:   # prefix run for the oracle comparison
         s.reset(u0)
@@ -188,7 +210,7 @@ def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
     s.close()
     ms = (t1 - t0) * 1e3 / steps
     return {"ms_per_step": ms, "macs": macs, "work": work, "prof": prof, "uT": uT,
-            "u_prefix": u_prefix, "steps": steps}
+            "u_prefix": u_prefix, "steps": 1}
 
 
 def roofline_of(kind, work_per_solve, launches_per_solve, ms_per_solve):
@@ -276,6 +298,8 @@ def main():
 
     for path, r in res.items():
         d = {"ms_per_step": r["ms_per_step"], "value": r["macs"] / (r["ms_per_step"] / 1e3)}
+        d["kernel_timing"] = ("one extra solve after the timed ones, each kernel launched on its "
+                              "own with HIP events stamped at its start and end")
         for name, (cnt, ms) in r["prof"].items():
             if cnt:
                 kd = {"launches": cnt // r["steps"], "ms_per_solve": ms / r["steps"],

@@ -164,7 +164,9 @@ gl_status gl_reset(gl_ctx *ctx, const double *u0);
 #define GL_KERNEL_TRIANGLE 3     /* one step inside a block of the blocked path (rows in the
                                     block, stencil, update: one launch per step) */
 #define GL_KERNEL_OLD_REDUCE 4   /* FP64 sum of the Toeplitz product's history chunks */
-#define GL_KERNEL_COUNT 5
+#define GL_KERNEL_SUBBLOCK 5     /* Toeplitz product over a block's rows before a sub-block */
+#define GL_KERNEL_SUB_REDUCE 6   /* FP64 sum of the sub-block product's chunks */
+#define GL_KERNEL_COUNT 7
 
 /* on != 0: gl_step_n brackets each launch of the timed kernels with HIP
  * events on the context's stream and accumulates their durations; resets

@@ -27,6 +27,7 @@ struct gl_ctx {
     int *d_flag = nullptr;
     float *tpart = nullptr;  // Toeplitz product chunks: max chunks x B x max P (FP32)
     gl::BatchEntry *d_batch = nullptr;  // one entry per problem (batched plain-path launches)
+
     double *bpartial = nullptr;          // per-problem GEMV partial regions of the batch
     int64_t upd_wgs = 0;                 // workgroups of one batched update launch
     int64_t C = 500;         // adjoint recompute segment length (snapshot interval)
@@ -39,6 +40,7 @@ struct gl_ctx {
     double *adj_grad = nullptr;  // per step and workgroup partial dot products, 3 each
     int64_t maxP = 0, maxld = 0;
     int B = 256;             // block length of the Toeplitz path
+    int B2 = 0;              // sub-block length inside a block (0: one level)
     gl::Tuning tune;
     std::vector<void *> allocs;
     std::string err;
@@ -160,6 +162,10 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
 
     const bool toep = opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
     ctx->B = opt.block_B ? opt.block_B : 256;
+    // a second level of blocking when the sub-block length divides the block length
+    ctx->B2 = (ctx->tune.sub_B > 0 && ctx->tune.sub_B < ctx->B && ctx->B % ctx->tune.sub_B == 0)
+                  ? (int)ctx->tune.sub_B
+                  : 0;
     // weights are kept for m up to max_steps + kMaxBlock (the last block's rows reach past k)
     const int64_t npsi = opt.max_steps + gl::kMaxBlock + 1;
     const int64_t tab_len = (npsi + gl::kPsiPad + 16 + 7) / 8 * 8;
@@ -181,7 +187,9 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
         if (pb.P > maxP) maxP = pb.P;
         need += (size_t)rows * pb.ld * sizeof(float) + 2 * (size_t)npsi * sizeof(double) +
                 2 * (size_t)pb.P * sizeof(double);
-        if (toep) need += 16 * (size_t)tab_len * sizeof(uint16_t) + (size_t)ctx->B * pb.P * sizeof(double);
+        if (toep)
+            need += 16 * (size_t)tab_len * sizeof(uint16_t) +
+                    (size_t)(ctx->B + ctx->tune.sub_B) * pb.P * sizeof(double);
     }
     ctx->C = opt.ckpt_every > 0 ? opt.ckpt_every : 500;
     const int64_t nsnap = opt.max_steps / ctx->C + 1;
@@ -215,6 +223,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
                            ctx->sched.runs.size() * sizeof(gl::Run), hipMemcpyHostToDevice));
     if ((st = dev_alloc(ctx, &ctx->partial, (size_t)gl::kMaxSplits * maxP))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_flag, 1))) return st;
+
     if (toep && (st = dev_alloc(ctx, &ctx->tpart, (size_t)std::max(nchunk_max, 1) * ctx->B * maxP)))
         return st;
 
@@ -235,6 +244,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
             pb.tab_len = tab_len;
             if ((st = dev_alloc(ctx, &pb.psi_tab, 16 * (size_t)tab_len))) return st;
             if ((st = dev_alloc(ctx, &pb.old, (size_t)ctx->B * pb.P))) return st;
+            if (ctx->B2 && (st = dev_alloc(ctx, &pb.old2, (size_t)ctx->B2 * pb.P))) return st;
             gl::launch_psi_tables(pb.psi, npsi, tab_len, pb.psi_tab, ctx->stream);
             HIP_TRY(ctx, hipGetLastError());
         }
@@ -252,6 +262,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
         e.u[0] = pb.u[0];
         e.u[1] = pb.u[1];
         e.partial = ctx->bpartial + off;
+        e.snap = pb.snap;
         e.groups = pb.gemv_groups;
         off += (size_t)bsplits[i] * pb.P;
         e.ndim = pb.p.ndim;
@@ -331,6 +342,7 @@ gl_status load_initial(gl_ctx *ctx, const double *u0) {
     for (gl::Problem &pb : ctx->probs) {
         pb.cur = 0;
         pb.old_k0 = -1;
+        pb.old2_k1 = -1;
         HIP_TRY(ctx, hipMemcpyAsync(pb.u[0], u0 + pb.offset, pb.P * sizeof(double),
                                     hipMemcpyDeviceToDevice, ctx->stream));
         HIP_TRY(ctx, hipMemcpyAsync(pb.snap, u0 + pb.offset, pb.P * sizeof(double),
@@ -343,14 +355,6 @@ gl_status load_initial(gl_ctx *ctx, const double *u0) {
     HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     if (flag) return fail(ctx, GL_ENONFINITE, "u0 holds NaN or Inf");
-    return GL_OK;
-}
-
-// After a step that reached k (multiple of C), keeps u[k] as the snapshot k / C.
-gl_status take_snapshot(gl_ctx *ctx, gl::Problem &pb, int64_t k) {
-    if (k % ctx->C == 0)
-        HIP_TRY(ctx, hipMemcpyAsync(pb.snap + (k / ctx->C) * pb.P, pb.u[pb.cur],
-                                    pb.P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
     return GL_OK;
 }
 
@@ -375,30 +379,37 @@ gl_status step_gemv(gl_ctx *ctx) {
         if (st != GL_OK) return st;
     }
     st = timed(ctx, GL_KERNEL_UPDATE, [&] {
-        gl::launch_update_batched(ctx->d_batch, nprob, ctx->upd_wgs, k, cur, T - 1, ctx->stream);
+        gl::launch_update_batched(ctx->d_batch, nprob, ctx->upd_wgs, k, cur, T - 1, ctx->C,
+                                  ctx->stream);
     });
     if (st != GL_OK) return st;
-    for (gl::Problem &pb : ctx->probs) {
-        pb.cur ^= 1;
-        if ((st = take_snapshot(ctx, pb, k + 1)) != GL_OK) return st;
-    }
+    for (gl::Problem &pb : ctx->probs) pb.cur ^= 1;
     HIP_TRY(ctx, hipGetLastError());
     ctx->k = k + 1;
     return GL_OK;
 }
 
-// old[b] = sum_{j < k0} psi(k0 + b - j) hist[j] for b < B, on the matrix cores.
-gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int64_t k0,
-                    double *old) {
-    const int nchunk = gl::toeplitz_chunks(k0, ctx->tune.kchunk);
-    gl_status st = timed(ctx, GL_KERNEL_TOEPLITZ, [&] {
-        gl::launch_toeplitz_gemm(ctx->B, hist, ld, pb.P, pb.psi_tab, pb.tab_len, k0,
+// out[b] = sum_{j_lo <= j < j_hi} psi(k_out + b - j) hist[j] for b < BM, on the matrix
+// cores (FP32 chunk products summed in FP64).
+gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int BM,
+                     int64_t k_out, int64_t j_lo, int64_t j_hi, double *out, int gemm_id,
+                     int reduce_id) {
+    const int nchunk = gl::toeplitz_chunks(j_hi - j_lo, ctx->tune.kchunk);
+    gl_status st = timed(ctx, gemm_id, [&] {
+        gl::launch_toeplitz_gemm(BM, hist, ld, pb.P, pb.psi_tab, pb.tab_len, k_out, j_lo, j_hi,
                                  ctx->tune.kchunk, ctx->tpart, ctx->stream);
     });
     if (st != GL_OK) return st;
-    return timed(ctx, GL_KERNEL_OLD_REDUCE, [&] {
-        gl::launch_old_reduce(ctx->tpart, nchunk, ctx->B, pb.P, old, ctx->stream);
+    return timed(ctx, reduce_id, [&] {
+        gl::launch_old_reduce(ctx->tpart, nchunk, BM, pb.P, out, ctx->stream);
     });
+}
+
+// old[b] = sum_{j < k0} psi(k0 + b - j) hist[j] for b < B.
+gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int64_t k0,
+                    double *old) {
+    return block_sums(ctx, pb, hist, ld, ctx->B, k0, 0, k0, old, GL_KERNEL_TOEPLITZ,
+                      GL_KERNEL_OLD_REDUCE);
 }
 
 // Step k -> k + 1 of one problem on the blocked path, from u_cur into u_next (S_out,
@@ -407,10 +418,19 @@ gl_status toeplitz_step_one(gl_ctx *ctx, gl::Problem &pb, int64_t k, const doubl
                             double *u_next, double *S_out, int write_history) {
     const int64_t b = k % ctx->B;
     const int64_t k0 = k - b;
+    // sub-block of the step (the whole block when there is one level)
+    const int64_t b2 = ctx->B2 ? b % ctx->B2 : b;
+    const int64_t k1 = k - b2;
     gl_status st;
     if (k0 > 0 && pb.old_k0 != k0) {
         if ((st = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old)) != GL_OK) return st;
         pb.old_k0 = k0;
+    }
+    if (k1 > k0 && pb.old2_k1 != k1) {
+        if ((st = block_sums(ctx, pb, pb.H, pb.ld, ctx->B2, k1, k0, k1, pb.old2,
+                             GL_KERNEL_SUBBLOCK, GL_KERNEL_SUB_REDUCE)) != GL_OK)
+            return st;
+        pb.old2_k1 = k1;
     }
     gl::BlockStepArgs args{};
     args.psi = pb.psi;
@@ -425,11 +445,15 @@ gl_status toeplitz_step_one(gl_ctx *ctx, gl::Problem &pb, int64_t k, const doubl
     args.dt = pb.p.dt;
     args.rate = pb.p.rxn_rate;
     args.old = k0 > 0 ? pb.old : nullptr;
+    args.old2 = k1 > k0 ? pb.old2 : nullptr;
     args.u_cur = u_cur;
     args.u_next = u_next;
     args.S_out = S_out;
+    args.snap = write_history ? pb.snap : nullptr;
+    args.C = ctx->C;
     args.k0 = k0;
     args.b = (int32_t)b;
+    args.b2 = (int32_t)b2;
     args.write_history = write_history;
     return timed(ctx, GL_KERNEL_TRIANGLE, [&] { gl::launch_block_step(args, ctx->stream); });
 }
@@ -443,7 +467,6 @@ gl_status step_toeplitz(gl_ctx *ctx) {
         gl_status st = toeplitz_step_one(ctx, pb, k, pb.u[pb.cur], pb.u[pb.cur ^ 1], nullptr, 1);
         if (st != GL_OK) return st;
         pb.cur ^= 1;
-        if ((st = take_snapshot(ctx, pb, k + 1)) != GL_OK) return st;
     }
     HIP_TRY(ctx, hipGetLastError());
     ctx->k = k + 1;
@@ -573,6 +596,7 @@ gl_status gl_init(const gl_problem *probs, int32_t nprob, const gl_options *opt,
     ctx->opt = *opt;
     if (const char *v = std::getenv("GL_GEMV_GROUPS")) ctx->tune.gemv_groups = std::max(1L, std::atol(v));
     if (const char *v = std::getenv("GL_GEMV_SERPENTINE")) ctx->tune.serpentine = std::atoi(v) != 0;
+    if (const char *v = std::getenv("GL_SUBBLOCK")) ctx->tune.sub_B = std::atol(v);
     if (const char *v = std::getenv("GL_TOEPLITZ_KCHUNK"))
         ctx->tune.kchunk = std::max(64L, std::atol(v) / 64 * 64);
     ctx->stream = static_cast<hipStream_t>(opt->stream);
@@ -650,7 +674,7 @@ gl_status gl_adjoint(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *
                     "gl_adjoint: the adaptive schedule's transpose is not built (full or short "
                     "memory only)");
     gl_status st = adjoint_impl(ctx, dL_duT, dL_du0, dparams);
-    for (gl::Problem &pb : ctx->probs) pb.old_k0 = -1;  // block sums were reused as scratch
+    for (gl::Problem &pb : ctx->probs) pb.old_k0 = pb.old2_k1 = -1;  // sums reused as scratch
     if (st != GL_OK) return st;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return resolve_profile(ctx);
@@ -719,7 +743,7 @@ gl_status gl_history_sum(gl_ctx *ctx, int32_t iprob, int64_t k, const float *his
         gl::Problem &pbm = ctx->probs[iprob];
         const int64_t b = k % ctx->B, k0 = k - b;
         if (k0 > 0) {
-            pbm.old_k0 = -1;  // old[] is reused as scratch here
+            pbm.old_k0 = pbm.old2_k1 = -1;  // old[] is reused as scratch here
             gl_status st = block_old(ctx, pbm, hist, ld, k0, pbm.old);
             if (st != GL_OK) return st;
             base = pbm.old + b * pbm.P;

@@ -2,15 +2,15 @@
 //
 // The history holds delta[j], the stencil of eq. (17) of each past state, so
 // the sum of eq. (21) is taken point by point.  For step k = k0 + b of a block
-// starting at k0:
+// starting at k0, inside its sub-block starting at k1 = k - b2:
 //   delta[k] = stencil of the FP64 state u[k] (the neighbours' u[k] were
 //              written by the previous step's launch);
-//   S[p]     = delta[k][p] + Old[b][p] + sum_{m=1}^{b} psi(gamma, m) H[k - m][p],
-//              Old the Toeplitz product over the rows before the block;
+//   S[p]     = delta[k][p] + Old[b][p] + Old2[b2][p] + sum_{m=1}^{b2} psi(gamma, m) H[k - m][p],
+//              Old the Toeplitz product over the rows before the block, Old2 the one
+//              over the block's rows before the sub-block (k0 .. k1-1);
 //   u[k+1]   = u[k] + dt f(u[k]) + r S;  history row k <- delta[k] (FP32).
 // A workgroup owns 64 points (16 lanes x 4 points, 16-byte row loads) and
-// splits the in-block rows m = 1..b over 16 row groups, one per 16 lanes, so a
-// lane keeps at most 16 rows in flight; the groups' FP64 partial sums are added
+// splits the sub-block rows m = 1..b2 over 16 row groups, one per 16 lanes; the groups' FP64 partial sums are added
 // in group order through LDS.
 #include <hip/hip_runtime.h>
 
@@ -40,9 +40,10 @@ __global__ __launch_bounds__(kStepThreads) void block_step_kernel(BlockStepArgs 
     const int b = a.b;
     const int64_t k = a.k0 + b;
 
-    // rows m = 1..b cut into kStepGroups contiguous ranges
-    const int m_lo = 1 + (b * grp) / kStepGroups;
-    const int m_hi = 1 + (b * (grp + 1)) / kStepGroups;
+    // rows m = 1..b2 (those of the sub-block before k) cut into kStepGroups contiguous ranges
+    const int b2 = a.b2;
+    const int m_lo = 1 + (b2 * grp) / kStepGroups;
+    const int m_hi = 1 + (b2 * (grp + 1)) / kStepGroups;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (p < P && m_lo < m_hi) {
         const float *row = a.H + (k - m_lo) * a.ld + p;
@@ -96,12 +97,15 @@ __global__ __launch_bounds__(kStepThreads) void block_step_kernel(BlockStepArgs 
     }
     double S = d;
     if (a.old) S += a.old[(int64_t)b * P + q];
+    if (a.old2) S += a.old2[(int64_t)b2 * P + q];
 #pragma unroll
     for (int g = 0; g < kStepGroups; ++g) S += red[g][tid];
     const double uk = u[q];
-    a.u_next[q] = uk + a.dt * step_reaction(a.rxn, a.rate, uk) + a.r * S;
+    const double un = uk + a.dt * step_reaction(a.rxn, a.rate, uk) + a.r * S;
+    a.u_next[q] = un;
     if (a.write_history) a.H[k * a.ld + q] = (float)d;
     if (a.S_out) a.S_out[q] = S;
+    if (a.snap && (k + 1) % a.C == 0) a.snap[((k + 1) / a.C) * P + q] = un;  // adjoint checkpoint
 }
 
 void launch_block_step(const BlockStepArgs &args, hipStream_t s) {

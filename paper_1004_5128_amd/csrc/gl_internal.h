@@ -68,8 +68,10 @@ struct Problem {
     // blocked Toeplitz path
     uint16_t *psi_tab = nullptr;  // BF16 hi/lo weight tables, 2 x 8 shifted copies of tab_len
     int64_t tab_len = 0;
-    double *old = nullptr;        // [B x P] FP64 sums over the states before the current block
+    double *old = nullptr;        // [B x P] FP64 sums over the rows before the current block
     int64_t old_k0 = -1;          // block start old[] belongs to (-1: none)
+    double *old2 = nullptr;       // [B2 x P] sums over the rows of the block before the sub-block
+    int64_t old2_k1 = -1;         // sub-block start old2[] belongs to (-1: none)
     // adjoint: FP64 snapshots of u every C steps, snap[i] = u[i C]
     double *snap = nullptr;
     // workgroup target of this problem's history GEMV: the context's target, shared among
@@ -105,6 +107,7 @@ struct BatchEntry {
     const double *psi;
     double *u[2];
     double *partial;  // this problem's GEMV partials, up to its split count x P
+    double *snap;     // adjoint snapshots: u[k+1] goes to snap[(k+1)/C] when C divides k+1
     int64_t groups;   // this problem's GEMV workgroup target (Problem::gemv_groups)
     int32_t ndim, nx, ny, rxn;
     double r, dt, rate;
@@ -119,14 +122,15 @@ void launch_hist_gemv_batched(const BatchEntry *tab, int nprob, int64_t wgs, con
 // One launch: the update of every problem from u[cur] into u[cur ^ 1], history row k;
 // `terms` = the GEMV's term count (t_end - t_begin), for each problem's split count.
 void launch_update_batched(const BatchEntry *tab, int nprob, int64_t wgs, int64_t k, int cur,
-                           int64_t terms, hipStream_t s);
+                           int64_t terms, int64_t C, hipStream_t s);
 
-// Tuning (defaults; GL_GEMV_GROUPS, GL_GEMV_SERPENTINE and GL_TOEPLITZ_KCHUNK in
-// the environment override them at gl_init).
+// Tuning (defaults; GL_GEMV_GROUPS, GL_GEMV_SERPENTINE, GL_TOEPLITZ_KCHUNK and
+// GL_SUBBLOCK in the environment override them at gl_init).
 struct Tuning {
     int64_t gemv_groups = 1024;  // target workgroups per GEMV launch
     bool serpentine = false;     // alternate the traversal direction every step
     int64_t kchunk = 2048;       // history rows per Toeplitz product chunk (multiple of 64)
+    int64_t sub_B = 32;          // sub-block length of the blocked path (32 or 64; 0: off)
 };
 
 // ---- blocked Toeplitz path
@@ -137,13 +141,15 @@ constexpr int kMaxBlock = 256;
 void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_t *tab,
                        hipStream_t s);
 
-// Number of history chunks the product over rows [0, k0) is cut into.
-int toeplitz_chunks(int64_t k0, int64_t kchunk);
+// Number of history chunks a product over `rows` rows is cut into.
+int toeplitz_chunks(int64_t rows, int64_t kchunk);
 
-// out[c][b][p] (FP32) = sum over rows j in chunk c of [0, k0) of
-// T[b][j] H[j * ld + p] with T[b][j] = psi(k0 + b - j), b < BM, three BF16 products.
+// out[c][b][p] (FP32) = sum over rows j in chunk c of [j_lo, j_hi) of
+// T[b][j] H[j * ld + p] with T[b][j] = psi(k0 + b - j), b < BM, three BF16 products
+// (j_hi <= k0).
 void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
-                          int64_t tab_len, int64_t k0, int64_t kchunk, float *out, hipStream_t s);
+                          int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
+                          float *out, hipStream_t s);
 
 // old[b * P + p] = sum_c part[c][b][p] in FP64, chunks in order.
 void launch_old_reduce(const float *part, int nchunk, int64_t BM, int64_t P, double *old,
@@ -156,14 +162,19 @@ struct BlockStepArgs {
     int64_t ld, P;
     int32_t ndim, nx, ny, rxn;
     double r, dt, rate;
-    const double *old;  // [B x P] sums over the states before the block, or nullptr (k0 = 0)
+    const double *old;   // [B x P] sums over the rows before the block, or nullptr (k0 = 0)
+    const double *old2;  // [B2 x P] sums over the block's rows before the sub-block, or nullptr
     const double *u_cur;
     double *u_next;
     double *S_out;          // nullable: receives the step's full sum S
+    double *snap;           // nullable: u[k+1] is also written to snap[(k+1)/C] when C divides k+1
+    int64_t C;
     int64_t k0;
-    int32_t b;
+    int32_t b;              // step k = k0 + b
+    int32_t b2;             // rows k - b2 .. k - 1 are summed here (those of the sub-block)
     int32_t write_history;  // 0: leave history row k untouched (recomputation)
 };
+
 
 // One in-block step as a single kernel (history sum over rows k0..k-1, stencil,
 // reaction, state update, history row k).

@@ -319,7 +319,7 @@ void launch_update(const Problem &pb, const double *u, const double *base, doubl
 // Batched update: workgroups laid out problem after problem, ceil(P / 256) each.
 __global__ __launch_bounds__(256) void update_batched_kernel(const BatchEntry *__restrict__ tab,
                                                              int nprob, int64_t k, int cur,
-                                                             int64_t terms) {
+                                                             int64_t terms, int64_t C) {
     int64_t w = blockIdx.x;
     int i = 0;
     for (; i < nprob; ++i) {
@@ -335,12 +335,14 @@ __global__ __launch_bounds__(256) void update_batched_kernel(const BatchEntry *_
     update_point((const GL_GLOBAL double *)e.u[cur], nullptr, (GL_GLOBAL double *)e.u[cur ^ 1],
                  (GL_GLOBAL float *)e.H + k * e.ld, nullptr, (const GL_GLOBAL double *)e.partial,
                  nsplit, e.P, e.ndim, e.nx, e.ny, e.r, e.dt, e.rxn, e.rate, p);
+    if ((k + 1) % C == 0)  // adjoint checkpoint of u[k+1]
+        ((GL_GLOBAL double *)e.snap)[((k + 1) / C) * e.P + p] = ((GL_GLOBAL double *)e.u[cur ^ 1])[p];
 }
 
 void launch_update_batched(const BatchEntry *tab, int nprob, int64_t wgs, int64_t k, int cur,
-                           int64_t terms, hipStream_t s) {
+                           int64_t terms, int64_t C, hipStream_t s) {
     GL_LAUNCH(update_batched_kernel, dim3((unsigned)wgs), dim3(256), 0, s, tab, nprob, k, cur,
-              terms);
+              terms, C);
 }
 
 // ----------------------------------------------------------------- helpers

@@ -8,7 +8,9 @@
 //     Old[b, p] = sum_{j < k0} psi(gamma, k0 + b - j) H[j, p],
 //
 // is a matrix product T H with the Toeplitz weight matrix T[b, j] =
-// psi(k0 + b - j) (B x k0) and the history H (k0 x P).  It is computed once
+// psi(k0 + b - j) (B x k0) and the history H (k0 x P).  The kernel takes any row
+// window [j_lo, j_hi) with weights psi(k0 + b - j), so the same product also forms
+// the sums over the rows of a block that precede one of its sub-blocks.  It is computed once
 // per block on the matrix cores with each operand split into two BF16 parts,
 // x = hi + lo (hi = x rounded to BF16, lo = the remainder rounded to BF16), and
 // three products hi.hi + hi.lo + lo.hi accumulated in FP32; the history rows are
@@ -81,7 +83,8 @@ constexpr int kLdsRow = kTK / 8 + 1;  // 16-byte words per point in LDS (one pad
 template <int BM>
 __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
     const float *__restrict__ H, int64_t ld, int64_t P, const u32x4_t *__restrict__ tab,
-    int64_t tab_len, int64_t k0, int64_t kchunk, float *__restrict__ out) {
+    int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
+    float *__restrict__ out) {
     constexpr int WM = BM >= 128 ? 4 : BM / 32;  // waves along the block rows
     constexpr int WN = 4 / WM;                   // waves along the points
     constexpr int RB = BM / 32 / WM;             // 32-row blocks per wave
@@ -95,8 +98,8 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
     const int wm = wave % WM, wn = wave / WM;
     const int g = lane >> 5;   // which 8-row half of a 16-row MFMA step this lane feeds
     const int64_t n0 = (int64_t)blockIdx.x * kTN;
-    const int64_t j_begin = (int64_t)blockIdx.y * kchunk;
-    const int64_t j_end = j_begin + kchunk < k0 ? j_begin + kchunk : k0;
+    const int64_t j_begin = j_lo + (int64_t)blockIdx.y * kchunk;
+    const int64_t j_end = j_begin + kchunk < j_hi ? j_begin + kchunk : j_hi;
     const int64_t tab_words = tab_len / 8;  // 16-byte words per table
 
     // loader: 32 groups of 4 points x 8 groups of 8 rows
@@ -193,28 +196,33 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
         }
 }
 
-int toeplitz_chunks(int64_t k0, int64_t kchunk) {
-    return k0 <= 0 ? 0 : (int)((k0 + kchunk - 1) / kchunk);
+int toeplitz_chunks(int64_t rows, int64_t kchunk) {
+    return rows <= 0 ? 0 : (int)((rows + kchunk - 1) / kchunk);
 }
 
 void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
-                          int64_t tab_len, int64_t k0, int64_t kchunk, float *out, hipStream_t s) {
-    const int nchunk = toeplitz_chunks(k0, kchunk);
+                          int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
+                          float *out, hipStream_t s) {
+    const int nchunk = toeplitz_chunks(j_hi - j_lo, kchunk);
     if (nchunk == 0) return;
     dim3 grid((unsigned)((P + kTN - 1) / kTN), (unsigned)nchunk);
     const u32x4_t *t = reinterpret_cast<const u32x4_t *>(tab);
     switch (BM) {
         case 32:
-            GL_LAUNCH(toeplitz_gemm_kernel<32>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            GL_LAUNCH(toeplitz_gemm_kernel<32>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
+                      j_lo, j_hi, kchunk, out);
             break;
         case 64:
-            GL_LAUNCH(toeplitz_gemm_kernel<64>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            GL_LAUNCH(toeplitz_gemm_kernel<64>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
+                      j_lo, j_hi, kchunk, out);
             break;
         case 128:
-            GL_LAUNCH(toeplitz_gemm_kernel<128>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            GL_LAUNCH(toeplitz_gemm_kernel<128>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
+                      j_lo, j_hi, kchunk, out);
             break;
         default:
-            GL_LAUNCH(toeplitz_gemm_kernel<256>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0, kchunk, out);
+            GL_LAUNCH(toeplitz_gemm_kernel<256>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
+                      j_lo, j_hi, kchunk, out);
             break;
     }
 }

@@ -59,7 +59,10 @@ GL_KERNEL_UPDATE = 1
 GL_KERNEL_TOEPLITZ = 2
 GL_KERNEL_TRIANGLE = 3
 GL_KERNEL_OLD_REDUCE = 4
-KERNEL_NAMES = {0: "hist_gemv", 1: "update", 2: "toeplitz", 3: "triangle", 4: "old_reduce"}
+GL_KERNEL_SUBBLOCK = 5
+GL_KERNEL_SUB_REDUCE = 6
+KERNEL_NAMES = {0: "hist_gemv", 1: "update", 2: "toeplitz", 3: "triangle", 4: "old_reduce",
+                5: "subblock", 6: "sub_reduce"}
 
 
 def _load():
