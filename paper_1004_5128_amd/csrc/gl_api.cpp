@@ -168,7 +168,9 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
                   : 0;
     // weights are kept for m up to max_steps + kMaxBlock (the last block's rows reach past k)
     const int64_t npsi = opt.max_steps + gl::kMaxBlock + 1;
-    const int64_t tab_len = (npsi + gl::kPsiPad + 16 + 7) / 8 * 8;
+    // table entries cover psi(-kPsiPad .. npsi + 63): a K step stages up to 8 words past the
+    // last index it uses
+    const int64_t tab_len = (npsi + gl::kPsiPad + 128 + 7) / 8 * 8;
     const int nchunk_max = gl::toeplitz_chunks(opt.max_steps, ctx->tune.kchunk);
 
     // capacity: history arena + tables + state

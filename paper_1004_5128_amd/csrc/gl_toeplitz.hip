@@ -69,8 +69,10 @@ void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_
 // transposed, [point][row], so that an MFMA B operand (8 consecutive rows of
 // one point) is one 16-byte LDS read.  Inside each group of 8 rows the order is
 // reversed, which makes the matching A operand (the weights of those rows for
-// one output row b) eight consecutive ascending psi values.  The next K step's
-// history loads are issued before the current step's MFMAs.
+// one output row b) eight consecutive ascending psi values, read from the slice of
+// the shifted weight tables the K step needs, staged in LDS beside the history.
+// The next K step's history and weight loads are issued before the current step's
+// MFMAs.
 //
 // v_mfma_f32_32x32x16_bf16 lane layout (wave64): A lane l holds row l%32,
 // k = 8(l/32)..+7; B lane l holds column l%32, the same k; the accumulator
@@ -79,6 +81,13 @@ void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_
 constexpr int kTN = 128;              // points per workgroup
 constexpr int kTK = 64;               // history rows per K step
 constexpr int kLdsRow = kTK / 8 + 1;  // 16-byte words per point in LDS (one pad word)
+
+// Weight words one K step reads from each of the 16 tables (hi/lo x 8 shifts): the
+// table indices of a step span BM + 63 entries starting at k0 - jt + 1.
+template <int BM>
+constexpr int psi_words() {
+    return (BM + 63 + 7) / 8 + 2;
+}
 
 template <int BM>
 __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
@@ -89,8 +98,12 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
     constexpr int WN = 4 / WM;                   // waves along the points
     constexpr int RB = BM / 32 / WM;             // 32-row blocks per wave
     constexpr int CB = kTN / 32 / WN;            // 32-point blocks per wave
+    constexpr int NW = psi_words<BM>();
+    constexpr int NPSI = 16 * NW;                         // weight words staged per K step
+    constexpr int PSI_PER_LANE = (NPSI + 255) / 256;
     __shared__ u32x4_t lhi[kTN * kLdsRow];
     __shared__ u32x4_t llo[kTN * kLdsRow];
+    __shared__ u32x4_t lpsi[NPSI];                        // [table 0..15][NW words]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -114,12 +127,23 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
         for (int j = 0; j < CB; ++j) acc[i][j] = f32x16_t{};
 
     float4 pre[8];
+    u32x4_t ppre[PSI_PER_LANE];
+    // first weight word of a K step: word of table index k0 - jt + 1, less one for slack
+    auto psi_w0 = [&](int64_t jt) { return (k0 - jt + 1) / 8 - 1; };
     auto load_tile = [&](int64_t jt) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int64_t row = jt + kg * 8 + e;
             pre[e] = (col_ok && row < j_end) ? *reinterpret_cast<const float4 *>(H + row * ld + col)
                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    };
+    auto load_psi = [&](int64_t jt) {
+        const int64_t w0 = psi_w0(jt);
+#pragma unroll
+        for (int i = 0; i < PSI_PER_LANE; ++i) {
+            const int idx = tid + i * 256;
+            if (idx < NPSI) ppre[i] = tab[(int64_t)(idx / NW) * tab_words + w0 + idx % NW];
         }
     };
     auto stage_tile = [&]() {
@@ -140,44 +164,54 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
             lhi[(ng * 4 + c) * kLdsRow + kg] = h4;
             llo[(ng * 4 + c) * kLdsRow + kg] = l4;
         }
+#pragma unroll
+        for (int i = 0; i < PSI_PER_LANE; ++i) {
+            const int idx = tid + i * 256;
+            if (idx < NPSI) lpsi[idx] = ppre[i];
+        }
     };
 
-    if (j_begin < j_end) load_tile(j_begin);
+    if (j_begin < j_end) {
+        load_tile(j_begin);
+        load_psi(j_begin);
+    }
     for (int64_t jt = j_begin; jt < j_end; jt += kTK) {
         __syncthreads();  // the previous step's MFMAs are done with LDS
         stage_tile();
         __syncthreads();
-        if (jt + kTK < j_end) load_tile(jt + kTK);
+        const bool more = jt + kTK < j_end;
+        if (more) load_tile(jt + kTK);
 #pragma unroll
         for (int q = 0; q < kTK / 16; ++q) {
-            u32x4_t bh[CB], bl[CB];
-#pragma unroll
-            for (int j = 0; j < CB; ++j) {
-                const int n = (wn * CB + j) * 32 + (lane & 31);
-                bh[j] = lhi[n * kLdsRow + 2 * q + g];
-                bl[j] = llo[n * kLdsRow + 2 * q + g];
-            }
+            // A operands of this 16-row step for the wave's row blocks: weights of rows
+            // jt+16q+8g+7-p, p = 0..7, i.e. psi(mstart + p), from the staged table slice
+            const int64_t w0 = psi_w0(jt);
+            bf16x8_t Ah[RB], Al[RB];
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 const int b = (wm * RB + i) * 32 + (lane & 31);
-                // weights of rows jt+16q+8g+7-p, p = 0..7: psi(mstart + p)
                 const int64_t idx = k0 + b - jt - 16 * q - 8 * g - 7 + kPsiPad;
                 const int s = (int)(idx & 7);
-                const int64_t w = (idx - s) >> 3;
-                const u32x4_t ah = tab[(int64_t)s * tab_words + w];
-                const u32x4_t al = tab[(int64_t)(8 + s) * tab_words + w];
-                const bf16x8_t Ah = __builtin_bit_cast(bf16x8_t, ah);
-                const bf16x8_t Al = __builtin_bit_cast(bf16x8_t, al);
+                const int w = (int)(((idx - s) >> 3) - w0);
+                Ah[i] = __builtin_bit_cast(bf16x8_t, lpsi[s * NW + w]);
+                Al[i] = __builtin_bit_cast(bf16x8_t, lpsi[(8 + s) * NW + w]);
+            }
+            // B operands one 32-point block at a time (fewer live registers)
 #pragma unroll
-                for (int j = 0; j < CB; ++j) {
-                    const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, bh[j]);
-                    const bf16x8_t Bl = __builtin_bit_cast(bf16x8_t, bl[j]);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al, Bh, acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bl, acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah, Bh, acc[i][j], 0, 0, 0);
+            for (int j = 0; j < CB; ++j) {
+                const int n = (wn * CB + j) * 32 + (lane & 31);
+                const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, lhi[n * kLdsRow + 2 * q + g]);
+                const bf16x8_t Bl = __builtin_bit_cast(bf16x8_t, llo[n * kLdsRow + 2 * q + g]);
+#pragma unroll
+                for (int i = 0; i < RB; ++i) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[i], Bh, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[i], Bl, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[i], Bh, acc[i][j], 0, 0, 0);
                 }
             }
         }
+        // the next step's weights: in flight across the barrier, not held during the MFMAs
+        if (more) load_psi(jt + kTK);
     }
 
     float *dst = out + (int64_t)blockIdx.y * BM * P;
@@ -205,6 +239,9 @@ void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const u
                           float *out, hipStream_t s) {
     const int nchunk = toeplitz_chunks(j_hi - j_lo, kchunk);
     if (nchunk == 0) return;
+    // K steps start 64-row aligned from j_lo; with k0 and j_lo multiples of 32 every step
+    // has k0 - jt >= 32, which keeps the staged weight words inside the tables
+    if (k0 % 32 != 0 || j_lo % 32 != 0 || j_hi > k0 || kchunk % kTK != 0) return;
     dim3 grid((unsigned)((P + kTN - 1) / kTN), (unsigned)nchunk);
     const u32x4_t *t = reinterpret_cast<const u32x4_t *>(tab);
     switch (BM) {
