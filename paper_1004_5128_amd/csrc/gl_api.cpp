@@ -414,15 +414,28 @@ gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld,
                       GL_KERNEL_OLD_REDUCE);
 }
 
-// Step k -> k + 1 of one problem on the blocked path, from u_cur into u_next (S_out,
-// nullable, receives the step's sum; write_history 0 leaves history row k alone).
-gl_status toeplitz_step_one(gl_ctx *ctx, gl::Problem &pb, int64_t k, const double *u_cur,
-                            double *u_next, double *S_out, int write_history) {
+// Steps of the blocked path that one launch can take from step k: at most the fusion
+// length, the steps left (limit) and those left in k's sub-block (its block with one level).
+int64_t block_run(const gl_ctx *ctx, int64_t k, int64_t limit) {
+    const int64_t b = k % ctx->B;
+    const int64_t left = ctx->B2 ? ctx->B2 - b % ctx->B2 : ctx->B - b;
+    return std::max<int64_t>(1, std::min({ctx->tune.fuse, limit, left}));
+}
+
+// Steps k .. k + s - 1 of one problem on the blocked path (s from block_run), from u_cur
+// into u_next; u_rows (nullable, stride u_stride) receives the states in between, S_out
+// (nullable, stride P) the steps' sums; write_history 0 leaves the history rows alone.
+gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
+                         const double *u_cur, double *u_next, double *u_rows, int64_t u_stride,
+                         double *S_out, int write_history) {
     const int64_t b = k % ctx->B;
     const int64_t k0 = k - b;
     // sub-block of the step (the whole block when there is one level)
     const int64_t b2 = ctx->B2 ? b % ctx->B2 : b;
     const int64_t k1 = k - b2;
+    if (s < 1 || s > gl::kMaxFuse || b2 + s > (ctx->B2 ? ctx->B2 : ctx->B))
+        return fail(ctx, GL_EINVAL, "internal: %lld in-block steps from step %lld",
+                    (long long)s, (long long)k);
     gl_status st;
     if (k0 > 0 && pb.old_k0 != k0) {
         if ((st = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old)) != GL_OK) return st;
@@ -450,28 +463,35 @@ gl_status toeplitz_step_one(gl_ctx *ctx, gl::Problem &pb, int64_t k, const doubl
     args.old2 = k1 > k0 ? pb.old2 : nullptr;
     args.u_cur = u_cur;
     args.u_next = u_next;
+    args.u_rows = u_rows;
+    args.u_stride = u_stride;
     args.S_out = S_out;
     args.snap = write_history ? pb.snap : nullptr;
     args.C = ctx->C;
-    args.k0 = k0;
+    args.k = k;
     args.b = (int32_t)b;
     args.b2 = (int32_t)b2;
+    args.s = (int32_t)s;
     args.write_history = write_history;
     return timed(ctx, GL_KERNEL_TRIANGLE, [&] { gl::launch_block_step(args, ctx->stream); });
 }
 
-// One step k -> k + 1 on the blocked path: at the start of each block of B steps the
-// sums over the states before the block are formed by the Toeplitz product; each step is
-// then one kernel (rows inside the block, stencil, update).
-gl_status step_toeplitz(gl_ctx *ctx) {
+// Up to `limit` steps on the blocked path (one launch per problem; *done receives the
+// count): at the start of each block of B steps the sums over the states before the block
+// are formed by the Toeplitz product, at each sub-block start the one over the block's rows
+// before it; the in-block steps then run several per kernel.
+gl_status step_toeplitz(gl_ctx *ctx, int64_t limit, int64_t *done) {
     const int64_t k = ctx->k;
+    const int64_t s = block_run(ctx, k, limit);
     for (gl::Problem &pb : ctx->probs) {
-        gl_status st = toeplitz_step_one(ctx, pb, k, pb.u[pb.cur], pb.u[pb.cur ^ 1], nullptr, 1);
+        gl_status st = toeplitz_steps(ctx, pb, k, s, pb.u[pb.cur], pb.u[pb.cur ^ 1], nullptr, 0,
+                                      nullptr, 1);
         if (st != GL_OK) return st;
         pb.cur ^= 1;
     }
     HIP_TRY(ctx, hipGetLastError());
-    ctx->k = k + 1;
+    ctx->k = k + s;
+    *done = s;
     return GL_OK;
 }
 
@@ -483,6 +503,16 @@ gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke
     HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_u, pb.snap + (ks / ctx->C) * P, P * sizeof(double),
                                 hipMemcpyDeviceToDevice, ctx->stream));
     const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
+    gl_status st;
+    if (toep) {
+        for (int64_t k = ks; k < ke;) {
+            const int64_t i = k - ks, s = block_run(ctx, k, ke - k);
+            if ((st = toeplitz_steps(ctx, pb, k, s, ctx->adj_u + i * P, ctx->adj_u + (i + s) * P,
+                                     ctx->adj_u + (i + 1) * P, P, ctx->adj_S + i * P, 0)) != GL_OK)
+                return st;
+            k += s;
+        }
+    }
     for (int64_t k = ks; k < ke; ++k) {
         const int64_t i = k - ks;
         const double *u = ctx->adj_u + i * P;
@@ -492,10 +522,7 @@ gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke
         const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
         const int64_t T = ctx->sched.terms[k];
         const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
-        gl_status st;
-        if (toep) {
-            if ((st = toeplitz_step_one(ctx, pb, k, u, un, S, 0)) != GL_OK) return st;
-        } else {
+        if (!toep) {
             const bool reverse = ctx->tune.serpentine && (k & 1);
             if (nsplit > 0)
                 gl::launch_hist_gemv(pb.H, pb.ld, P, pb.psi, ctx->d_runs + rb, nruns, k, 1, T,
@@ -599,6 +626,8 @@ gl_status gl_init(const gl_problem *probs, int32_t nprob, const gl_options *opt,
     if (const char *v = std::getenv("GL_GEMV_GROUPS")) ctx->tune.gemv_groups = std::max(1L, std::atol(v));
     if (const char *v = std::getenv("GL_GEMV_SERPENTINE")) ctx->tune.serpentine = std::atoi(v) != 0;
     if (const char *v = std::getenv("GL_SUBBLOCK")) ctx->tune.sub_B = std::atol(v);
+    if (const char *v = std::getenv("GL_FUSE"))
+        ctx->tune.fuse = std::min<int64_t>(gl::kMaxFuse, std::max(1L, std::atol(v)));
     if (const char *v = std::getenv("GL_TOEPLITZ_KCHUNK"))
         ctx->tune.kchunk = std::max(64L, std::atol(v) / 64 * 64);
     ctx->stream = static_cast<hipStream_t>(opt->stream);
@@ -621,8 +650,11 @@ gl_status gl_step_n(gl_ctx *ctx, int64_t n, double *uT) {
                     (long long)ctx->k, (long long)n, (long long)ctx->opt.max_steps);
     gl_status st;
     const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
-    for (int64_t s = 0; s < n; ++s)
-        if ((st = toep ? step_toeplitz(ctx) : step_gemv(ctx)) != GL_OK) return st;
+    for (int64_t s = 0; s < n;) {
+        int64_t done = 1;
+        if ((st = toep ? step_toeplitz(ctx, n - s, &done) : step_gemv(ctx)) != GL_OK) return st;
+        s += done;
+    }
     if (uT && (st = copy_state(ctx, uT)) != GL_OK) return st;
     if (ctx->opt.check_finite) {
         HIP_TRY(ctx, hipMemsetAsync(ctx->d_flag, 0, sizeof(int), ctx->stream));

@@ -1,17 +1,24 @@
-// One step of the blocked path inside a block, as a single kernel.
+// In-block steps of the blocked path, several per launch.
 //
-// The history holds delta[j], the stencil of eq. (17) of each past state, so
-// the sum of eq. (21) is taken point by point.  For step k = k0 + b of a block
-// starting at k0, inside its sub-block starting at k1 = k - b2:
-//   delta[k] = stencil of the FP64 state u[k] (the neighbours' u[k] were
-//              written by the previous step's launch);
-//   S[p]     = delta[k][p] + Old[b][p] + Old2[b2][p] + sum_{m=1}^{b2} psi(gamma, m) H[k - m][p],
-//              Old the Toeplitz product over the rows before the block, Old2 the one
-//              over the block's rows before the sub-block (k0 .. k1-1);
-//   u[k+1]   = u[k] + dt f(u[k]) + r S;  history row k <- delta[k] (FP32).
-// A workgroup owns 64 points (16 lanes x 4 points, 16-byte row loads) and
-// splits the sub-block rows m = 1..b2 over 16 row groups, one per 16 lanes; the groups' FP64 partial sums are added
-// in group order through LDS.
+// The history holds delta[j], the stencil of eq. (17) of each past state, so the sum of
+// eq. (21) is taken point by point.  For step kk in a block starting at k0 and a sub-block
+// starting at k1 (b = kk - k0, b2 = kk - k1):
+//   acc     = Old[b][p] + Old2[b2][p], then acc = fma(psi(gamma, kk - j), delta[j][p], acc)
+//             for j = k1 .. kk-1 in ascending order (one chain);
+//   S[p]    = acc + delta[kk][p], delta[kk] the FP64 stencil of u[kk] (zero outside the grid);
+//   u[kk+1] = u[kk] + dt f(u[kk]) + r S;  history row kk <- (float) delta[kk].
+// Old is the Toeplitz product over the rows before the block, Old2 the one over the block's
+// rows before the sub-block (either absent when it has no rows).
+//
+// One launch takes s steps k .. k+s-1 of a sub-block.  A workgroup owns a tile of points
+// (16 x 16 in 2D, 256 in 1D) and recomputes a halo around it: step i is evaluated on the
+// tile widened by S-1-i points (S >= s, the compile-time halo), which needs u[k+i] one point
+// further out, so u[k] is read on the tile widened by S and the states stay in LDS from step
+// to step.  The delta rows of the launch's own steps stay in the registers of the lane that
+// owns the point; rows before k come from the history.  A halo point repeats its owner's
+// arithmetic in the same order, so all copies of a value are bit-identical, and because the
+// chain above does not depend on where a launch starts, any grouping of the steps into
+// launches gives the same bits (the adjoint's recomputation relies on this).
 #include <hip/hip_runtime.h>
 
 #include "gl_internal.h"
@@ -19,9 +26,18 @@
 namespace gl {
 
 constexpr int kStepThreads = 256;
-constexpr int kStepGroups = 16;
-constexpr int kStepLanes = kStepThreads / kStepGroups;  // 16
-constexpr int kStepPoints = kStepLanes * 4;             // 64 points per workgroup
+constexpr int kTile2 = 16;   // 2D tile side
+constexpr int kTile1 = 256;  // 1D tile length
+constexpr int kRowBatch = 8; // history rows loaded together
+
+template <int S>
+struct StepGeom {
+    static constexpr int kUSide = kTile2 + 2 * S;                 // 2D u region side
+    static constexpr int kULen = kUSide * kUSide;                 // >= kTile1 + 2 S
+    static constexpr int kR0 = (kTile2 + 2 * (S - 1)) * (kTile2 + 2 * (S - 1));  // >= 1D's
+    static constexpr int kPts = (kR0 + kStepThreads - 1) / kStepThreads;       // per lane
+    static_assert(kULen >= kTile1 + 2 * S && kR0 >= kTile1 + 2 * (S - 1), "1D fits 2D sizes");
+};
 
 __device__ __forceinline__ double step_reaction(int rxn, double rate, double u) {
     if (rxn == GL_RXN_LINEAR) return -rate * u;
@@ -29,88 +45,156 @@ __device__ __forceinline__ double step_reaction(int rxn, double rate, double u) 
     return 0.0;
 }
 
-__global__ __launch_bounds__(kStepThreads) void block_step_kernel(BlockStepArgs a) {
-    __shared__ double red[kStepGroups][kStepPoints];
+template <int S>
+__global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs a) {
+    using G = StepGeom<S>;
+    __shared__ double lu[2][G::kULen];
     const int tid = threadIdx.x;
-    const int grp = tid / kStepLanes;
-    const int lane = tid % kStepLanes;
-    const int64_t P = a.P;
-    const int64_t p0 = (int64_t)blockIdx.x * kStepPoints;
-    const int64_t p = p0 + lane * 4;
-    const int b = a.b;
-    const int64_t k = a.k0 + b;
+    const bool two = a.ndim == 2;
+    const int tx = two ? kTile2 : kTile1, ty = two ? kTile2 : 1, hy = two ? 1 : 0;
+    const int uw = tx + 2 * S, uh = ty + 2 * S * hy;              // u region
+    const int w0 = tx + 2 * (S - 1), h0 = ty + 2 * (S - 1) * hy;  // step-0 region
+    const int64_t nx = a.nx, ny = two ? a.ny : 1, P = a.P;
+    const int ntx = (int)((nx + tx - 1) / tx);
+    const int64_t gx0 = (int64_t)(two ? blockIdx.x % ntx : blockIdx.x) * tx - S;
+    const int64_t gy0 = two ? (int64_t)(blockIdx.x / ntx) * ty - S : 0;
+    const int s = a.s;
+    const int64_t k = a.k;
 
-    // rows m = 1..b2 (those of the sub-block before k) cut into kStepGroups contiguous ranges
-    const int b2 = a.b2;
-    const int m_lo = 1 + (b2 * grp) / kStepGroups;
-    const int m_hi = 1 + (b2 * (grp + 1)) / kStepGroups;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    if (p < P && m_lo < m_hi) {
-        const float *row = a.H + (k - m_lo) * a.ld + p;
-        int m = m_lo;
-        for (; m + 8 <= m_hi; m += 8) {
-            float4 v[8];
+    for (int idx = tid; idx < uw * uh; idx += kStepThreads) {
+        const int64_t gx = gx0 + idx % uw, gy = gy0 + idx / uw;
+        const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        lu[0][idx] = in ? a.u_cur[gy * nx + gx] : 0.0;
+        lu[1][idx] = 0.0;
+    }
+
+    // the lane's points: slot n is point tid + n * 256 of the step-0 region
+    int ux[G::kPts];       // index in the u region
+    int lvl[G::kPts];      // evaluated at steps i <= lvl (distance to the step-0 region's
+                           // edge); -1: no grid point in this slot
+    int64_t q[G::kPts];    // grid index
 #pragma unroll
-            for (int i = 0; i < 8; ++i) v[i] = *reinterpret_cast<const float4 *>(row - (int64_t)i * a.ld);
+    for (int n = 0; n < G::kPts; ++n) {
+        const int r = tid + n * kStepThreads;
+        const int rx = r % w0, ry = r / w0;
+        const int64_t gx = gx0 + rx + 1, gy = gy0 + ry + hy;
+        const bool ok = r < w0 * h0 && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        int l = min(rx, w0 - 1 - rx);
+        if (two) l = min(l, min(ry, h0 - 1 - ry));
+        lvl[n] = ok ? l : -1;
+        ux[n] = (ry + hy) * uw + rx + 1;
+        q[n] = ok ? gy * nx + gx : 0;
+    }
+
+    // Chains of the s steps up to row k - 1: Old + Old2, then the sub-block's rows.  Loads
+    // are unconditional so that they issue together: slots without a grid point read point
+    // 0 and steps past s re-read step s - 1's row (both unused).
+    double acc[G::kPts][S];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const double w = a.psi[m + i];
-                s0 = fma(w, (double)v[i].x, s0);
-                s1 = fma(w, (double)v[i].y, s1);
-                s2 = fma(w, (double)v[i].z, s2);
-                s3 = fma(w, (double)v[i].w, s3);
+    for (int n = 0; n < G::kPts; ++n)
+#pragma unroll
+        for (int i = 0; i < S; ++i) acc[n][i] = 0.0;
+    if (a.old) {
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const double *o = a.old + (int64_t)(a.b + min(i, s - 1)) * P;
+#pragma unroll
+            for (int n = 0; n < G::kPts; ++n) acc[n][i] = o[q[n]];
+        }
+    }
+    if (a.old2) {
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const double *o = a.old2 + (int64_t)(a.b2 + min(i, s - 1)) * P;
+#pragma unroll
+            for (int n = 0; n < G::kPts; ++n) acc[n][i] += o[q[n]];
+        }
+    }
+    const int nr = a.b2;  // rows k - nr .. k - 1
+    const float *rows = a.H + (k - nr) * a.ld;
+    int j = 0;
+    for (; j + kRowBatch <= nr; j += kRowBatch) {
+        float v[G::kPts][kRowBatch];
+#pragma unroll
+        for (int n = 0; n < G::kPts; ++n)
+#pragma unroll
+            for (int t = 0; t < kRowBatch; ++t) v[n][t] = rows[(int64_t)(j + t) * a.ld + q[n]];
+        // row j + t is kk - (nr - j - t) steps back from step kk = k + i
+        double w[kRowBatch + S - 1];
+#pragma unroll
+        for (int x = 0; x < kRowBatch + S - 1; ++x)
+            w[x] = x < kRowBatch + s - 1 ? a.psi[nr - j - (kRowBatch - 1) + x] : 0.0;
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t)
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+#pragma unroll
+                for (int n = 0; n < G::kPts; ++n)
+                    acc[n][i] = fma(w[kRowBatch - 1 - t + i], (double)v[n][t], acc[n][i]);
+    }
+    for (; j < nr; ++j) {
+        float v[G::kPts];
+#pragma unroll
+        for (int n = 0; n < G::kPts; ++n) v[n] = rows[(int64_t)j * a.ld + q[n]];
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            const double wi = i < s ? a.psi[nr - j + i] : 0.0;
+#pragma unroll
+            for (int n = 0; n < G::kPts; ++n) acc[n][i] = fma(wi, (double)v[n], acc[n][i]);
+        }
+    }
+    double wl[S];  // psi(1 .. S-1) for this launch's own rows
+#pragma unroll
+    for (int m = 1; m < S; ++m) wl[m] = m < s ? a.psi[m] : 0.0;
+    wl[0] = 0.0;
+
+    float dl[G::kPts][S];  // the lane's delta rows k .. k + i - 1, FP32 as stored
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        if (i >= s) break;
+        __syncthreads();  // u[k + i] complete in lu[i & 1]; its readers of step i - 1 done
+        const double *uc = lu[i & 1];
+        double *un = lu[(i & 1) ^ 1];
+        const int64_t kk = k + i;
+#pragma unroll
+        for (int n = 0; n < G::kPts; ++n) {
+            if (lvl[n] < i) continue;
+            const int x = ux[n];
+            const double u = uc[x];
+            const double d = two ? uc[x + 1] + uc[x - 1] - 4.0 * u + uc[x + uw] + uc[x - uw]
+                                 : uc[x + 1] - 2.0 * u + uc[x - 1];
+            double c = acc[n][i];
+#pragma unroll
+            for (int i2 = 0; i2 < i; ++i2) c = fma(wl[i - i2], (double)dl[n][i2], c);
+            const float df = (float)d;
+            dl[n][i] = df;
+            const double Sv = c + d;
+            const double unew = u + a.dt * step_reaction(a.rxn, a.rate, u) + a.r * Sv;
+            un[x] = unew;
+            if (lvl[n] >= S - 1) {  // a point of the tile: results go out
+                if (a.write_history) a.H[kk * a.ld + q[n]] = df;
+                if (a.S_out) a.S_out[(int64_t)i * P + q[n]] = Sv;
+                if (i == s - 1) a.u_next[q[n]] = unew;
+                else if (a.u_rows) a.u_rows[(int64_t)i * a.u_stride + q[n]] = unew;
+                if (a.snap && (kk + 1) % a.C == 0) a.snap[((kk + 1) / a.C) * P + q[n]] = unew;
             }
-            row -= 8 * a.ld;
-        }
-        for (; m < m_hi; ++m) {
-            const float4 v = *reinterpret_cast<const float4 *>(row);
-            const double w = a.psi[m];
-            s0 = fma(w, (double)v.x, s0);
-            s1 = fma(w, (double)v.y, s1);
-            s2 = fma(w, (double)v.z, s2);
-            s3 = fma(w, (double)v.w, s3);
-            row -= a.ld;
         }
     }
-    red[grp][lane * 4 + 0] = s0;
-    red[grp][lane * 4 + 1] = s1;
-    red[grp][lane * 4 + 2] = s2;
-    red[grp][lane * 4 + 3] = s3;
-    __syncthreads();
-    if (tid >= kStepPoints) return;
-    const int64_t q = p0 + tid;
-    if (q >= P) return;
-
-    double d;  // stencil of eq. (17), zero outside the grid
-    const double *u = a.u_cur;
-    if (a.ndim == 1) {
-        const double e = q + 1 < P ? u[q + 1] : 0.0;
-        const double w = q > 0 ? u[q - 1] : 0.0;
-        d = e - 2.0 * u[q] + w;
-    } else {
-        const int64_t x = q % a.nx, y = q / a.nx;
-        const double e = x + 1 < a.nx ? u[q + 1] : 0.0;
-        const double w = x > 0 ? u[q - 1] : 0.0;
-        const double n = y + 1 < a.ny ? u[q + a.nx] : 0.0;
-        const double s = y > 0 ? u[q - a.nx] : 0.0;
-        d = e + w - 4.0 * u[q] + n + s;
-    }
-    double S = d;
-    if (a.old) S += a.old[(int64_t)b * P + q];
-    if (a.old2) S += a.old2[(int64_t)b2 * P + q];
-#pragma unroll
-    for (int g = 0; g < kStepGroups; ++g) S += red[g][tid];
-    const double uk = u[q];
-    const double un = uk + a.dt * step_reaction(a.rxn, a.rate, uk) + a.r * S;
-    a.u_next[q] = un;
-    if (a.write_history) a.H[k * a.ld + q] = (float)d;
-    if (a.S_out) a.S_out[q] = S;
-    if (a.snap && (k + 1) % a.C == 0) a.snap[((k + 1) / a.C) * P + q] = un;  // adjoint checkpoint
 }
 
 void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
-    const unsigned groups = (unsigned)((args.P + kStepPoints - 1) / kStepPoints);
-    GL_LAUNCH(block_step_kernel, dim3(groups), dim3(kStepThreads), 0, s, args);
+    const int64_t ntiles = args.ndim == 2
+                               ? ((args.nx + kTile2 - 1) / kTile2) * ((args.ny + kTile2 - 1) / kTile2)
+                               : (args.nx + kTile1 - 1) / kTile1;
+    const dim3 grid((unsigned)ntiles), block(kStepThreads);
+    if (args.s <= 1)
+        GL_LAUNCH(block_steps_kernel<1>, grid, block, 0, s, args);
+    else if (args.s <= 2)
+        GL_LAUNCH(block_steps_kernel<2>, grid, block, 0, s, args);
+    else if (args.s <= 4)
+        GL_LAUNCH(block_steps_kernel<4>, grid, block, 0, s, args);
+    else
+        GL_LAUNCH(block_steps_kernel<8>, grid, block, 0, s, args);
 }
 
 }  // namespace gl

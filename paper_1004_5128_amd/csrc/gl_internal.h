@@ -131,6 +131,7 @@ struct Tuning {
     bool serpentine = false;     // alternate the traversal direction every step
     int64_t kchunk = 2048;       // history rows per Toeplitz product chunk (multiple of 64)
     int64_t sub_B = 32;          // sub-block length of the blocked path (32 or 64; 0: off)
+    int64_t fuse = 8;            // in-block steps per launch (1 .. kMaxFuse)
 };
 
 // ---- blocked Toeplitz path
@@ -164,20 +165,26 @@ struct BlockStepArgs {
     double r, dt, rate;
     const double *old;   // [B x P] sums over the rows before the block, or nullptr (k0 = 0)
     const double *old2;  // [B2 x P] sums over the block's rows before the sub-block, or nullptr
-    const double *u_cur;
-    double *u_next;
-    double *S_out;          // nullable: receives the step's full sum S
-    double *snap;           // nullable: u[k+1] is also written to snap[(k+1)/C] when C divides k+1
+    const double *u_cur;    // u[k]
+    double *u_next;         // u[k + s]
+    double *u_rows;         // nullable: u[k + i + 1] for i < s - 1 at u_rows + i * u_stride
+    int64_t u_stride;
+    double *S_out;          // nullable: row i (stride P) receives the full sum S of step k + i
+    double *snap;           // nullable: u[j] is also written to snap[j / C] when C divides j
     int64_t C;
-    int64_t k0;
-    int32_t b;              // step k = k0 + b
-    int32_t b2;             // rows k - b2 .. k - 1 are summed here (those of the sub-block)
-    int32_t write_history;  // 0: leave history row k untouched (recomputation)
+    int64_t k;              // first step of the launch
+    int32_t b;              // k - k0 (offset in the block: row of old)
+    int32_t b2;             // k - k1 (offset in the sub-block: row of old2; rows k1 .. k - 1
+                            // are summed point by point)
+    int32_t s;              // steps in this launch (1 .. kMaxFuse), inside one sub-block
+    int32_t write_history;  // 0: leave history rows k .. k + s - 1 untouched (recomputation)
 };
 
+constexpr int kMaxFuse = 8;
 
-// One in-block step as a single kernel (history sum over rows k0..k-1, stencil,
-// reaction, state update, history row k).
+// Steps k .. k + s - 1 of one sub-block as a single kernel (history sums over the
+// sub-block's rows, stencil, reaction, state update, history rows).  The result of every
+// step does not depend on how steps are grouped into launches.
 void launch_block_step(const BlockStepArgs &args, hipStream_t s);
 
 // S[p] = sum_s partial[s * P + p] (+ base[p] if base != nullptr), fixed order.

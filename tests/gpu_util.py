@@ -50,3 +50,17 @@ def gemv_groups(value):
             del os.environ["GL_GEMV_GROUPS"]
         else:
             os.environ["GL_GEMV_GROUPS"] = old
+
+
+@contextlib.contextmanager
+def env(name, value):
+    """Set an environment variable the library reads when a solver is created."""
+    old = os.environ.get(name)
+    os.environ[name] = str(value)
+    try:
+        yield
+    finally:
+        if old is None:
+            del os.environ[name]
+        else:
+            os.environ[name] = old

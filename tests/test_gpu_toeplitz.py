@@ -1,13 +1,14 @@
 """Parity of the blocked Toeplitz path (history before each block of B steps summed as
 one BF16 hi/lo x 3 matrix product with FP32 accumulation, FP64 chunk sums; each step
-inside the block one kernel) with the FP64 oracle.  Tolerance: relative L2 <= 1e-5."""
+inside a sub-block up to eight per kernel) with the FP64 oracle.  Tolerance: relative
+L2 <= 1e-5."""
 import numpy as np
 import pytest
 import torch
 
 import oracle
 from paper_1004_5128_amd import workloads as W
-from gpu_util import gl, gpu_run, print_case, rel_l2
+from gpu_util import env, gl, gpu_run, print_case, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -103,6 +104,34 @@ def test_split_calls_equal_one_call():
         s.step(157)
         two = s.step(343).cpu().numpy()
     assert np.array_equal(one, two)
+
+
+@pytest.mark.parametrize("dims,B,sub", [((2, 37, 23), 64, 32), ((2, 48, 48), 256, 32),
+                                         ((1, 600, 1), 32, 32), ((2, 20, 17), 128, 0),
+                                         ((1, 300, 1), 256, 64)])
+def test_fused_steps_do_not_depend_on_grouping(dims, B, sub):
+    # the in-block steps taken 1, 3 or 8 per launch, and the run cut into calls of odd
+    # lengths, give the same bits: each step's sum is one chain that does not depend on
+    # where a launch starts (sub = 0: one level, rows up to B - 1 summed in the step kernel)
+    ndim, nx, ny = dims
+    p = W.problem(ndim, nx, 0.65, 0.8, 0.1, rxn="fisher", rate=0.7)
+    p["ny"] = ny
+    u0 = W.uniform_field(p, 5)
+    n = 700
+    print_case("fused grouping", dims, B, sub)
+    outs = []
+    with env("GL_SUBBLOCK", sub):
+        for fuse in (1, 3, 8):
+            with env("GL_FUSE", fuse):
+                outs.append(gpu_run(p, W.memory("full"), u0, n, sum_path="toeplitz", block_B=B))
+        with env("GL_FUSE", 8), gl().Solver(p, W.memory("full"), torch.as_tensor(u0),
+                                             max_steps=n, sum_path="toeplitz", block_B=B) as s:
+            for c in (5, 1, 13, 7, 3, 250, 421):
+                out = s.step(c)
+            outs.append(out.cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert rel_l2(outs[0], oracle.run(p, W.memory("full"), u0, n)) <= TOL_MFMA
 
 
 def test_toeplitz_needs_full_memory():
