@@ -137,34 +137,77 @@ def sub_block(B):
     return B2 if 0 < B2 < B and B % B2 == 0 else 0
 
 
+def kchunk():
+    """History rows per Toeplitz product chunk (GL_TOEPLITZ_KCHUNK, default 8192)."""
+    v = os.environ.get("GL_TOEPLITZ_KCHUNK")
+    return max(64, int(v) // 64 * 64) if v else 8192
+
+
+def fuse():
+    """In-block steps per launch (GL_FUSE, default 8)."""
+    v = os.environ.get("GL_FUSE")
+    return min(8, max(1, int(v))) if v else 8
+
+
+def block_launches(n, B):
+    """(first step, steps) of each in-block launch of an n-step run, as the library groups them:
+    at most fuse() steps, never across a sub-block (a block with one level)."""
+    B2 = sub_block(B)
+    out, k = [], 0
+    while k < n:
+        left = B2 - (k % B) % B2 if B2 else B - k % B
+        s = max(1, min(fuse(), n - k, left))
+        out.append((k, s))
+        k += s
+    return out
+
+
 def algorithmic_work(path, P, n, B, terms):
     """Algorithmic work of each kernel over one solve of n steps (see the design notes):
      hist_gemv:  every history row of terms m >= 1 read once, 4 bytes per point
      update:     u[k] read, u[k+1] and the FP32 history row k written (20 bytes per point)
      toeplitz:   6 flops (three BF16 products) per (block row, history row, point); its HBM
-                 side: history rows read once, FP32 chunk products written
-     triangle:   one in-block step: the sub-block's rows before the step (4 bytes each), u read
-                 and written, history row written, each block sum read (8 bytes) once present
-     subblock:   the product over a block's rows before a sub-block (as toeplitz)
-     old_reduce, sub_reduce: the FP32 chunk products read, the FP64 sums written"""
+                 side: history rows read once, then FP32 chunk products written, or the FP64
+                 sums themselves when the rows fit one chunk
+     triangle:   one in-block launch of s steps: the sub-block's rows before the launch (4
+                 bytes each), u read and written once, s history rows written, the s rows of
+                 the block sums read (8 bytes) once any exist
+     subblock:   the product over a block's rows before a sub-block (as toeplitz), its FP64
+                 sums written, the block sums of its rows read as their base
+     old_reduce, sub_reduce: the FP32 chunk products read, the FP64 sums written (only
+                 for products of more than one chunk)"""
     work = {"hist_gemv": ("hbm", 4 * P * sum(t - 1 for t in terms)),
             "update": ("hbm", 20 * P * n)}
     if path == "toeplitz":
+        kc = kchunk()
+        chunks = lambda rows: -(-rows // kc)
         blocks = range(B, n, B)
         work["toeplitz"] = ("mfma", 6 * B * P * sum(blocks))
-        work["toeplitz_bytes"] = ("hbm", P * sum(4 * k0 + 4 * B * -(-k0 // 2048) for k0 in blocks))
+        work["toeplitz_bytes"] = ("hbm", P * sum(4 * k0 + (8 * B if chunks(k0) == 1 else
+                                                           4 * B * chunks(k0)) for k0 in blocks))
         B2 = sub_block(B)
-        inner = [(k % B) % B2 if B2 else k % B for k in range(n)]   # rows summed by the step
-        work["triangle"] = ("hbm", P * sum(4 * b2 + 20 + (8 if k >= B else 0) +
-                                           (8 if (k % B) - b2 > 0 else 0)
-                                           for k, b2 in zip(range(n), inner)))
-        work["old_reduce"] = ("hbm", B * P * sum(4 * -(-k0 // 2048) + 8 for k0 in blocks))
+        tri = 0
+        for k, s in block_launches(n, B):
+            b = k % B
+            b2 = b % B2 if B2 else b
+            has_pre = k >= B or b - b2 > 0
+            tri += 4 * b2 + 16 + 4 * s + (8 * s if has_pre else 0)
+        work["triangle"] = ("hbm", P * tri)
+        multi = [k0 for k0 in blocks if chunks(k0) > 1]
+        if multi:
+            work["old_reduce"] = ("hbm", B * P * sum(4 * chunks(k0) + 8 for k0 in multi))
         if B2:
             # sub-block products: rows k0 .. k1-1 for every sub-block start k1 > k0 (< n)
-            rows = [k1 % B for k1 in range(B2, n, B2) if k1 % B]
-            work["subblock"] = ("mfma", 6 * B2 * P * sum(rows))
-            work["subblock_bytes"] = ("hbm", P * sum(4 * r + 4 * B2 for r in rows))
-            work["sub_reduce"] = ("hbm", B2 * P * 12 * len(rows))
+            starts = [k1 for k1 in range(B2, n, B2) if k1 % B]
+            work["subblock"] = ("mfma", 6 * B2 * P * sum(k1 % B for k1 in starts))
+            base = lambda k1: 8 * B2 if k1 >= B else 0   # block sums read as the base
+            work["subblock_bytes"] = ("hbm", P * sum(
+                4 * (k1 % B) + (8 * B2 + base(k1) if chunks(k1 % B) == 1 else
+                                4 * B2 * chunks(k1 % B)) for k1 in starts))
+            multi2 = [k1 for k1 in starts if chunks(k1 % B) > 1]
+            if multi2:
+                work["sub_reduce"] = ("hbm", P * sum(B2 * (4 * chunks(k1 % B) + 8) + base(k1)
+                                                     for k1 in multi2))
     return work
 
 

@@ -393,24 +393,27 @@ gl_status step_gemv(gl_ctx *ctx) {
 
 // out[b] = sum_{j_lo <= j < j_hi} psi(k_out + b - j) hist[j] for b < BM, on the matrix
 // cores (FP32 chunk products summed in FP64).
+// (base[b] +) out[b] = sum_{j_lo <= j < j_hi} psi(k_out + b - j) hist[j] for b < BM, on the
+// matrix cores (FP32 chunk products summed in FP64; one chunk is written by the product
+// kernel itself).
 gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int BM,
-                     int64_t k_out, int64_t j_lo, int64_t j_hi, double *out, int gemm_id,
-                     int reduce_id) {
+                     int64_t k_out, int64_t j_lo, int64_t j_hi, double *out, const double *base,
+                     int gemm_id, int reduce_id) {
     const int nchunk = gl::toeplitz_chunks(j_hi - j_lo, ctx->tune.kchunk);
     gl_status st = timed(ctx, gemm_id, [&] {
         gl::launch_toeplitz_gemm(BM, hist, ld, pb.P, pb.psi_tab, pb.tab_len, k_out, j_lo, j_hi,
-                                 ctx->tune.kchunk, ctx->tpart, ctx->stream);
+                                 ctx->tune.kchunk, ctx->tpart, out, base, ctx->stream);
     });
-    if (st != GL_OK) return st;
+    if (st != GL_OK || nchunk <= 1) return st;
     return timed(ctx, reduce_id, [&] {
-        gl::launch_old_reduce(ctx->tpart, nchunk, BM, pb.P, out, ctx->stream);
+        gl::launch_old_reduce(ctx->tpart, nchunk, BM, pb.P, out, base, ctx->stream);
     });
 }
 
 // old[b] = sum_{j < k0} psi(k0 + b - j) hist[j] for b < B.
 gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int64_t k0,
                     double *old) {
-    return block_sums(ctx, pb, hist, ld, ctx->B, k0, 0, k0, old, GL_KERNEL_TOEPLITZ,
+    return block_sums(ctx, pb, hist, ld, ctx->B, k0, 0, k0, old, nullptr, GL_KERNEL_TOEPLITZ,
                       GL_KERNEL_OLD_REDUCE);
 }
 
@@ -442,8 +445,10 @@ gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
         pb.old_k0 = k0;
     }
     if (k1 > k0 && pb.old2_k1 != k1) {
+        // Old2 holds Old (rows of the sub-block's steps) + the product over rows k0 .. k1-1
         if ((st = block_sums(ctx, pb, pb.H, pb.ld, ctx->B2, k1, k0, k1, pb.old2,
-                             GL_KERNEL_SUBBLOCK, GL_KERNEL_SUB_REDUCE)) != GL_OK)
+                             k0 > 0 ? pb.old + (k1 - k0) * pb.P : nullptr, GL_KERNEL_SUBBLOCK,
+                             GL_KERNEL_SUB_REDUCE)) != GL_OK)
             return st;
         pb.old2_k1 = k1;
     }
@@ -459,15 +464,22 @@ gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
     args.r = pb.r;
     args.dt = pb.p.dt;
     args.rate = pb.p.rxn_rate;
-    args.old = k0 > 0 ? pb.old : nullptr;
-    args.old2 = k1 > k0 ? pb.old2 : nullptr;
+    args.has_pre = k1 > k0 || k0 > 0;
+    args.pre = k1 > k0 ? pb.old2 : pb.old;
+    args.pre_row = (int32_t)(k1 > k0 ? b2 : b);
     args.u_cur = u_cur;
     args.u_next = u_next;
     args.u_rows = u_rows;
     args.u_stride = u_stride;
     args.S_out = S_out;
-    args.snap = write_history ? pb.snap : nullptr;
-    args.C = ctx->C;
+    if (write_history && pb.snap) {
+        args.snap = pb.snap;
+        for (int64_t i = s - 1; i >= 0; --i)
+            if ((k + i + 1) % ctx->C == 0) {
+                args.snap_mask |= 1u << i;
+                args.snap_row0 = (k + i + 1) / ctx->C;
+            }
+    }
     args.k = k;
     args.b = (int32_t)b;
     args.b2 = (int32_t)b2;

@@ -8,7 +8,8 @@
 //   S[p]    = acc + delta[kk][p], delta[kk] the FP64 stencil of u[kk] (zero outside the grid);
 //   u[kk+1] = u[kk] + dt f(u[kk]) + r S;  history row kk <- (float) delta[kk].
 // Old is the Toeplitz product over the rows before the block, Old2 the one over the block's
-// rows before the sub-block (either absent when it has no rows).
+// rows before the sub-block (either absent when it has no rows); the product kernels hand
+// over their sum Old + Old2 as one array.
 //
 // One launch takes s steps k .. k+s-1 of a sub-block.  A workgroup owns a tile of points
 // (16 x 16 in 2D, 256 in 1D) and recomputes a halo around it: step i is evaluated on the
@@ -25,10 +26,11 @@
 
 namespace gl {
 
-constexpr int kStepThreads = 256;
+constexpr int kStepThreads = 1024;
 constexpr int kTile2 = 16;   // 2D tile side
 constexpr int kTile1 = 256;  // 1D tile length
-constexpr int kRowBatch = 8; // history rows loaded together
+constexpr int kRowBatch = 32; // history rows loaded together
+constexpr int kWin = 16;      // rows per weight window
 
 template <int S>
 struct StepGeom {
@@ -38,6 +40,17 @@ struct StepGeom {
     static constexpr int kPts = (kR0 + kStepThreads - 1) / kStepThreads;       // per lane
     static_assert(kULen >= kTile1 + 2 * S && kR0 >= kTile1 + 2 * (S - 1), "1D fits 2D sizes");
 };
+
+// Workgroups are dispatched to the 8 XCDs in turn (id mod 8), each XCD with its own L2.
+// Giving XCD x a contiguous run of tiles (in row-major tile order: a band of the grid) keeps
+// the halos its workgroups read mostly inside its own band, so overlapping reads hit its L2
+// instead of every XCD fetching most of the grid.  A bijection on 0 .. n-1.
+__device__ __forceinline__ int xcd_tile(int id, int n) {
+    constexpr int kXcd = 8;
+    const int q = n / kXcd, r = n % kXcd;
+    const int x = id % kXcd, local = id / kXcd;
+    return x * q + min(x, r) + local;
+}
 
 __device__ __forceinline__ double step_reaction(int rxn, double rate, double u) {
     if (rxn == GL_RXN_LINEAR) return -rate * u;
@@ -56,16 +69,23 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
     const int w0 = tx + 2 * (S - 1), h0 = ty + 2 * (S - 1) * hy;  // step-0 region
     const int64_t nx = a.nx, ny = two ? a.ny : 1, P = a.P;
     const int ntx = (int)((nx + tx - 1) / tx);
-    const int64_t gx0 = (int64_t)(two ? blockIdx.x % ntx : blockIdx.x) * tx - S;
-    const int64_t gy0 = two ? (int64_t)(blockIdx.x / ntx) * ty - S : 0;
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int64_t gx0 = (int64_t)(two ? tile % ntx : tile) * tx - S;
+    const int64_t gy0 = two ? (int64_t)(tile / ntx) * ty - S : 0;
     const int s = a.s;
     const int64_t k = a.k;
 
-    for (int idx = tid; idx < uw * uh; idx += kStepThreads) {
+    // u[k] on the u region (zero outside the grid), held in registers until the history
+    // loads below are in flight too
+    constexpr int kULoads = (G::kULen + kStepThreads - 1) / kStepThreads;
+    double uv[kULoads];
+    bool uin[kULoads];
+#pragma unroll
+    for (int c = 0; c < kULoads; ++c) {
+        const int idx = tid + c * kStepThreads;
         const int64_t gx = gx0 + idx % uw, gy = gy0 + idx / uw;
-        const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        lu[0][idx] = in ? a.u_cur[gy * nx + gx] : 0.0;
-        lu[1][idx] = 0.0;
+        uin[c] = idx < uw * uh && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        uv[c] = a.u_cur[uin[c] ? gy * nx + gx : 0];
     }
 
     // the lane's points: slot n is point tid + n * 256 of the step-0 region
@@ -86,67 +106,93 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
         q[n] = ok ? gy * nx + gx : 0;
     }
 
-    // Chains of the s steps up to row k - 1: Old + Old2, then the sub-block's rows.  Loads
-    // are unconditional so that they issue together: slots without a grid point read point
-    // 0 and steps past s re-read step s - 1's row (both unused).
+    // Chains of the s steps up to row k - 1: Old + Old2, then the sub-block's rows.  All loads
+    // are issued before any is used and are unconditional: slots without a grid point read
+    // point 0, steps past s re-read step s - 1's row, rows past the last re-read it (all
+    // unused).  Addresses are a uniform row base plus the lane's 32-bit byte offset.
+    uint32_t qb8[G::kPts], qb4[G::kPts];
+#pragma unroll
+    for (int n = 0; n < G::kPts; ++n) {
+        qb8[n] = (uint32_t)q[n] * 8u;
+        qb4[n] = (uint32_t)q[n] * 4u;
+    }
+    double pv[G::kPts][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const char *o = reinterpret_cast<const char *>(a.pre + (int64_t)(a.pre_row + min(i, s - 1)) * P);
+#pragma unroll
+        for (int n = 0; n < G::kPts; ++n) pv[n][i] = *reinterpret_cast<const double *>(o + qb8[n]);
+    }
+    const int nr = a.b2;  // rows k - nr .. k - 1
+    const float *rows = a.H + (k - nr) * a.ld;
+    float v[G::kPts][kRowBatch];
+    auto load_rows = [&](int j) {
+        // groups of 8 rows holding at least one row of the batch (uniform branches, so the
+        // loads still issue together)
+#pragma unroll
+        for (int g8 = 0; g8 < kRowBatch / 8; ++g8) {
+            if (j + 8 * g8 < nr) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int t = 8 * g8 + e;
+                    const char *row =
+                        reinterpret_cast<const char *>(rows + (int64_t)min(j + t, nr - 1) * a.ld);
+#pragma unroll
+                    for (int n = 0; n < G::kPts; ++n)
+                        v[n][t] = *reinterpret_cast<const float *>(row + qb4[n]);
+                }
+            }
+        }
+    };
+    load_rows(0);
     double acc[G::kPts][S];
 #pragma unroll
     for (int n = 0; n < G::kPts; ++n)
 #pragma unroll
-        for (int i = 0; i < S; ++i) acc[n][i] = 0.0;
-    if (a.old) {
-#pragma unroll
         for (int i = 0; i < S; ++i) {
-            const double *o = a.old + (int64_t)(a.b + min(i, s - 1)) * P;
-#pragma unroll
-            for (int n = 0; n < G::kPts; ++n) acc[n][i] = o[q[n]];
+            acc[n][i] = 0.0;
+            acc[n][i] += a.has_pre ? pv[n][i] : 0.0;
         }
-    }
-    if (a.old2) {
+    for (int j = 0; j < nr; j += kRowBatch) {
+        if (j > 0) load_rows(j);
 #pragma unroll
-        for (int i = 0; i < S; ++i) {
-            const double *o = a.old2 + (int64_t)(a.b2 + min(i, s - 1)) * P;
+        for (int h = 0; h < kRowBatch / kWin; ++h) {
+            const int j0 = j + h * kWin;
+            if (j0 >= nr) continue;
+            // row j0 + t is m = nr - j0 - t + i steps back from step k + i: the weights of
+            // kWin rows and S steps are psi(nr - j0 - kWin + 1 .. nr - j0 + S - 1)
+            double w[kWin + S - 1];
 #pragma unroll
-            for (int n = 0; n < G::kPts; ++n) acc[n][i] += o[q[n]];
-        }
-    }
-    const int nr = a.b2;  // rows k - nr .. k - 1
-    const float *rows = a.H + (k - nr) * a.ld;
-    int j = 0;
-    for (; j + kRowBatch <= nr; j += kRowBatch) {
-        float v[G::kPts][kRowBatch];
+            for (int x = 0; x < kWin + S - 1; ++x) w[x] = a.psi[max(nr - j0 - (kWin - 1) + x, 0)];
 #pragma unroll
-        for (int n = 0; n < G::kPts; ++n)
+            for (int t = 0; t < kWin; ++t) {
+                if (j0 + t < nr) {
 #pragma unroll
-            for (int t = 0; t < kRowBatch; ++t) v[n][t] = rows[(int64_t)(j + t) * a.ld + q[n]];
-        // row j + t is kk - (nr - j - t) steps back from step kk = k + i
-        double w[kRowBatch + S - 1];
+                    for (int i = 0; i < S; ++i) {
+                        if (i < s) {
 #pragma unroll
-        for (int x = 0; x < kRowBatch + S - 1; ++x)
-            w[x] = x < kRowBatch + s - 1 ? a.psi[nr - j - (kRowBatch - 1) + x] : 0.0;
-#pragma unroll
-        for (int t = 0; t < kRowBatch; ++t)
-#pragma unroll
-            for (int i = 0; i < S; ++i)
-#pragma unroll
-                for (int n = 0; n < G::kPts; ++n)
-                    acc[n][i] = fma(w[kRowBatch - 1 - t + i], (double)v[n][t], acc[n][i]);
-    }
-    for (; j < nr; ++j) {
-        float v[G::kPts];
-#pragma unroll
-        for (int n = 0; n < G::kPts; ++n) v[n] = rows[(int64_t)j * a.ld + q[n]];
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            const double wi = i < s ? a.psi[nr - j + i] : 0.0;
-#pragma unroll
-            for (int n = 0; n < G::kPts; ++n) acc[n][i] = fma(wi, (double)v[n], acc[n][i]);
+                            for (int n = 0; n < G::kPts; ++n)
+                                acc[n][i] = fma(w[kWin - 1 - t + i], (double)v[n][h * kWin + t],
+                                                acc[n][i]);
+                        }
+                    }
+                }
+            }
         }
     }
     double wl[S];  // psi(1 .. S-1) for this launch's own rows
 #pragma unroll
     for (int m = 1; m < S; ++m) wl[m] = m < s ? a.psi[m] : 0.0;
     wl[0] = 0.0;
+
+#pragma unroll
+    for (int c = 0; c < kULoads; ++c) {
+        const int idx = tid + c * kStepThreads;
+        if (idx < uw * uh) {
+            lu[0][idx] = uin[c] ? uv[c] : 0.0;
+            lu[1][idx] = 0.0;
+        }
+    }
 
     float dl[G::kPts][S];  // the lane's delta rows k .. k + i - 1, FP32 as stored
 #pragma unroll
@@ -176,7 +222,9 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
                 if (a.S_out) a.S_out[(int64_t)i * P + q[n]] = Sv;
                 if (i == s - 1) a.u_next[q[n]] = unew;
                 else if (a.u_rows) a.u_rows[(int64_t)i * a.u_stride + q[n]] = unew;
-                if (a.snap && (kk + 1) % a.C == 0) a.snap[((kk + 1) / a.C) * P + q[n]] = unew;
+                if ((a.snap_mask >> i) & 1u)
+                    a.snap[(a.snap_row0 + __builtin_popcount(a.snap_mask & ((1u << i) - 1u))) * P +
+                           q[n]] = unew;
             }
         }
     }

@@ -129,7 +129,7 @@ void launch_update_batched(const BatchEntry *tab, int nprob, int64_t wgs, int64_
 struct Tuning {
     int64_t gemv_groups = 1024;  // target workgroups per GEMV launch
     bool serpentine = false;     // alternate the traversal direction every step
-    int64_t kchunk = 2048;       // history rows per Toeplitz product chunk (multiple of 64)
+    int64_t kchunk = 8192;       // history rows per Toeplitz product chunk (multiple of 64)
     int64_t sub_B = 32;          // sub-block length of the blocked path (32 or 64; 0: off)
     int64_t fuse = 8;            // in-block steps per launch (1 .. kMaxFuse)
 };
@@ -147,31 +147,38 @@ int toeplitz_chunks(int64_t rows, int64_t kchunk);
 
 // out[c][b][p] (FP32) = sum over rows j in chunk c of [j_lo, j_hi) of
 // T[b][j] H[j * ld + p] with T[b][j] = psi(k0 + b - j), b < BM, three BF16 products
-// (j_hi <= k0).
+// (j_hi <= k0).  With one chunk and direct != nullptr the FP64 result (what the chunk
+// reduction below gives, plus base[b][p] when base != nullptr) goes to direct[b][p] instead.
 void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
                           int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
-                          float *out, hipStream_t s);
+                          float *out, double *direct, const double *base, hipStream_t s);
 
-// old[b * P + p] = sum_c part[c][b][p] in FP64, chunks in order.
+// old[b * P + p] = (base[b * P + p] +) sum_c part[c][b][p] in FP64, chunks in order.
 void launch_old_reduce(const float *part, int nchunk, int64_t BM, int64_t P, double *old,
-                       hipStream_t s);
+                       const double *base, hipStream_t s);
 
-// Arguments of the in-block step kernel: step k0 + b of one problem.
+// Arguments of the in-block step kernel: steps k .. k + s - 1 of one problem.
 struct BlockStepArgs {
     const double *psi;
     float *H;
     int64_t ld, P;
     int32_t ndim, nx, ny, rxn;
     double r, dt, rate;
-    const double *old;   // [B x P] sums over the rows before the block, or nullptr (k0 = 0)
-    const double *old2;  // [B2 x P] sums over the block's rows before the sub-block, or nullptr
+    // Sums over the rows before the sub-block: row pre_row + i belongs to step k + i.  The
+    // block's product Old ([B x P], row b) in the first sub-block of a block, Old + the
+    // sub-block's product over the block's earlier rows ([B2 x P], row b2) after it.  Before
+    // any row exists has_pre is 0 and pre is still a readable [B x P] array (not used).
+    const double *pre;
+    int32_t pre_row;
+    int32_t has_pre;
     const double *u_cur;    // u[k]
     double *u_next;         // u[k + s]
     double *u_rows;         // nullable: u[k + i + 1] for i < s - 1 at u_rows + i * u_stride
     int64_t u_stride;
     double *S_out;          // nullable: row i (stride P) receives the full sum S of step k + i
-    double *snap;           // nullable: u[j] is also written to snap[j / C] when C divides j
-    int64_t C;
+    double *snap;           // nullable: checkpoint rows of u (row j / C holds u[j])
+    uint32_t snap_mask;     // bit i: C divides k + i + 1, u[k + i + 1] goes to a checkpoint
+    int64_t snap_row0;      // checkpoint row of the lowest set bit (the next ones follow)
     int64_t k;              // first step of the launch
     int32_t b;              // k - k0 (offset in the block: row of old)
     int32_t b2;             // k - k1 (offset in the sub-block: row of old2; rows k1 .. k - 1

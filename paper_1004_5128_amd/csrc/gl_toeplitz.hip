@@ -25,6 +25,8 @@
 namespace gl {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
@@ -74,6 +76,11 @@ void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_
 // The next K step's history and weight loads are issued before the current step's
 // MFMAs.
 //
+// LDS row r holds point 4 (r % 32) + r / 32 of the tile, so column c of 32-point block j is
+// point 4c + j: the transposed stores (a lane's four consecutive points go to rows 32 apart)
+// and the B reads (consecutive lanes, consecutive rows) both walk the rows with an odd word
+// stride, free of bank conflicts.
+//
 // v_mfma_f32_32x32x16_bf16 lane layout (wave64): A lane l holds row l%32,
 // k = 8(l/32)..+7; B lane l holds column l%32, the same k; the accumulator
 // lane l holds column l%32, rows 8(r/4) + 4(l/32) + r%4 for r = 0..15.
@@ -93,7 +100,7 @@ template <int BM>
 __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
     const float *__restrict__ H, int64_t ld, int64_t P, const u32x4_t *__restrict__ tab,
     int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
-    float *__restrict__ out) {
+    float *__restrict__ out, double *__restrict__ direct, const double *__restrict__ base) {
     constexpr int WM = BM >= 128 ? 4 : BM / 32;  // waves along the block rows
     constexpr int WN = 4 / WM;                   // waves along the points
     constexpr int RB = BM / 32 / WM;             // 32-row blocks per wave
@@ -126,6 +133,27 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
 #pragma unroll
         for (int j = 0; j < CB; ++j) acc[i][j] = f32x16_t{};
 
+    // the base of a direct (one-chunk) product, fetched at the start for the small row
+    // blocks of the sub-block products (registers to spare), at the end otherwise
+    constexpr bool kBaseFirst = BM <= 64;
+    double bpre[kBaseFirst ? RB : 1][kBaseFirst ? CB : 1][16];
+    if constexpr (kBaseFirst) {
+        if (direct && base) {
+#pragma unroll
+            for (int i = 0; i < RB; ++i)
+#pragma unroll
+                for (int j = 0; j < CB; ++j) {
+                    const int64_t n = n0 + 4 * (lane & 31) + (wn * CB + j);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        bpre[i][j][r] =
+                            n < P ? base[(int64_t)((wm * RB + i) * 32 + 8 * (r / 4) + 4 * g +
+                                                   (r % 4)) * P + n]
+                                  : 0.0;
+                }
+        }
+    }
+
     float4 pre[8];
     u32x4_t ppre[PSI_PER_LANE];
     // first weight word of a K step: word of table index k0 - jt + 1, less one for slack
@@ -149,20 +177,25 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
     auto stage_tile = [&]() {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            uint32_t hb[8], lb[8];
+            float v[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const float v = c == 0 ? pre[e].x : c == 1 ? pre[e].y : c == 2 ? pre[e].z : pre[e].w;
-                hb[e] = bf16_bits(v);
-                lb[e] = bf16_bits(v - __uint_as_float(hb[e] << 16));
+            for (int e = 0; e < 8; ++e)
+                v[e] = c == 0 ? pre[e].x : c == 1 ? pre[e].y : c == 2 ? pre[e].z : pre[e].w;
+            // element p of the group holds row 7 - p: word w packs rows 7 - 2w (low half) and
+            // 6 - 2w; hi rounded to nearest even by the packed conversion, lo the same of the
+            // (exact) remainder
+            u32x4_t h4, l4;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const f32x2_t x = {v[7 - 2 * w], v[6 - 2 * w]};
+                const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2_t));
+                const f32x2_t hx = {__uint_as_float(hb << 16), __uint_as_float(hb & 0xffff0000u)};
+                h4[w] = hb;
+                l4[w] = __builtin_bit_cast(uint32_t, __builtin_convertvector(x - hx, bf16x2_t));
             }
-            // element p of the group holds row 7 - p
-            const u32x4_t h4 = {hb[7] | (hb[6] << 16), hb[5] | (hb[4] << 16), hb[3] | (hb[2] << 16),
-                                hb[1] | (hb[0] << 16)};
-            const u32x4_t l4 = {lb[7] | (lb[6] << 16), lb[5] | (lb[4] << 16), lb[3] | (lb[2] << 16),
-                                lb[1] | (lb[0] << 16)};
-            lhi[(ng * 4 + c) * kLdsRow + kg] = h4;
-            llo[(ng * 4 + c) * kLdsRow + kg] = l4;
+            // point 4 ng + c lives in LDS row 32 c + ng (see the layout note above)
+            lhi[(c * 32 + ng) * kLdsRow + kg] = h4;
+            llo[(c * 32 + ng) * kLdsRow + kg] = l4;
         }
 #pragma unroll
         for (int i = 0; i < PSI_PER_LANE; ++i) {
@@ -214,12 +247,38 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
         if (more) load_psi(jt + kTK);
     }
 
+    if (direct) {
+        // one chunk: the FP64 sum itself (what the chunk reduction gives for one chunk)
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = 0; j < CB; ++j) {
+                const int64_t n = n0 + 4 * (lane & 31) + (wn * CB + j);
+                if (n < P) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t e = (int64_t)((wm * RB + i) * 32 + 8 * (r / 4) + 4 * g +
+                                                    (r % 4)) * P + n;
+                        double v = 0.0;
+                        v += (double)acc[i][j][r];
+                        if (base) {
+                            if constexpr (kBaseFirst)
+                                v = bpre[i][j][r] + v;
+                            else
+                                v = base[e] + v;
+                        }
+                        direct[e] = v;
+                    }
+                }
+            }
+        return;
+    }
     float *dst = out + (int64_t)blockIdx.y * BM * P;
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < CB; ++j) {
-            const int64_t n = n0 + (wn * CB + j) * 32 + (lane & 31);
+            const int64_t n = n0 + 4 * (lane & 31) + (wn * CB + j);
             if (n < P) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
@@ -236,49 +295,50 @@ int toeplitz_chunks(int64_t rows, int64_t kchunk) {
 
 void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
                           int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
-                          float *out, hipStream_t s) {
+                          float *out, double *direct, const double *base, hipStream_t s) {
     const int nchunk = toeplitz_chunks(j_hi - j_lo, kchunk);
     if (nchunk == 0) return;
     // K steps start 64-row aligned from j_lo; with k0 and j_lo multiples of 32 every step
     // has k0 - jt >= 32, which keeps the staged weight words inside the tables
     if (k0 % 32 != 0 || j_lo % 32 != 0 || j_hi > k0 || kchunk % kTK != 0) return;
+    if (nchunk > 1) direct = nullptr;  // the chunk reduction writes the sums
     dim3 grid((unsigned)((P + kTN - 1) / kTN), (unsigned)nchunk);
     const u32x4_t *t = reinterpret_cast<const u32x4_t *>(tab);
     switch (BM) {
         case 32:
             GL_LAUNCH(toeplitz_gemm_kernel<32>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
-                      j_lo, j_hi, kchunk, out);
+                      j_lo, j_hi, kchunk, out, direct, base);
             break;
         case 64:
             GL_LAUNCH(toeplitz_gemm_kernel<64>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
-                      j_lo, j_hi, kchunk, out);
+                      j_lo, j_hi, kchunk, out, direct, base);
             break;
         case 128:
             GL_LAUNCH(toeplitz_gemm_kernel<128>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
-                      j_lo, j_hi, kchunk, out);
+                      j_lo, j_hi, kchunk, out, direct, base);
             break;
         default:
             GL_LAUNCH(toeplitz_gemm_kernel<256>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
-                      j_lo, j_hi, kchunk, out);
+                      j_lo, j_hi, kchunk, out, direct, base);
             break;
     }
 }
 
 // Old[b * P + p] = sum over chunks c (in order) of part[(c * BM + b) * P + p], FP64.
 __global__ void old_reduce_kernel(const float *__restrict__ part, int nchunk, int64_t BP,
-                                  double *__restrict__ old) {
+                                  double *__restrict__ old, const double *__restrict__ base) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= BP) return;
     double s = 0.0;
     for (int c = 0; c < nchunk; ++c) s += (double)part[(int64_t)c * BP + i];
-    old[i] = s;
+    old[i] = base ? base[i] + s : s;
 }
 
 void launch_old_reduce(const float *part, int nchunk, int64_t BM, int64_t P, double *old,
-                       hipStream_t s) {
+                       const double *base, hipStream_t s) {
     const int64_t BP = BM * P;
     GL_LAUNCH(old_reduce_kernel, dim3((unsigned)((BP + 255) / 256)), dim3(256), 0, s, part,
-                       nchunk, BP, old);
+                       nchunk, BP, old, base);
 }
 
 }  // namespace gl
