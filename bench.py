@@ -137,10 +137,21 @@ def sub_block(B):
     return B2 if 0 < B2 < B and B % B2 == 0 else 0
 
 
-def kchunk():
-    """History rows per Toeplitz product chunk (GL_TOEPLITZ_KCHUNK, default 8192)."""
+def toeplitz_chunks(rows, BM, P):
+    """Chunks of a Toeplitz product over `rows` history rows, as the library cuts it: rows of
+    GL_TOEPLITZ_KCHUNK if set, else the fewest chunks whose workgroups (128-point column
+    tiles x chunks) fill the GPU, two per CU (one for the 512-row block)."""
     v = os.environ.get("GL_TOEPLITZ_KCHUNK")
-    return max(64, int(v) // 64 * 64) if v else 8192
+    if v:
+        kc = max(128, int(v) // 128 * 128)
+    else:
+        import torch
+        ncu = torch.cuda.get_device_properties(0).multi_processor_count
+        tiles = -(-P // 128)
+        target = ncu * (1 if BM >= 512 else 2)
+        n = max(1, min(-(-target // tiles), -(-rows // 128)))
+        kc = -(-(-(-max(rows, 1) // n)) // 128) * 128
+    return -(-rows // kc) if rows > 0 else 0
 
 
 def fuse():
@@ -179,13 +190,12 @@ def algorithmic_work(path, P, n, B, terms):
     work = {"hist_gemv": ("hbm", 4 * P * sum(t - 1 for t in terms)),
             "update": ("hbm", 20 * P * n)}
     if path == "toeplitz":
-        kc = kchunk()
-        chunks = lambda rows: -(-rows // kc)
         blocks = range(B, n, B)
+        B2 = sub_block(B)
+        chunks = lambda rows, BM=B: toeplitz_chunks(rows, BM, P)
         work["toeplitz"] = ("mfma", 6 * B * P * sum(blocks))
         work["toeplitz_bytes"] = ("hbm", P * sum(4 * k0 + (8 * B if chunks(k0) == 1 else
                                                            4 * B * chunks(k0)) for k0 in blocks))
-        B2 = sub_block(B)
         tri = 0
         for k, s in block_launches(n, B):
             b = k % B
@@ -202,11 +212,11 @@ def algorithmic_work(path, P, n, B, terms):
             work["subblock"] = ("mfma", 6 * B2 * P * sum(k1 % B for k1 in starts))
             base = lambda k1: 8 * B2 if k1 >= B else 0   # block sums read as the base
             work["subblock_bytes"] = ("hbm", P * sum(
-                4 * (k1 % B) + (8 * B2 + base(k1) if chunks(k1 % B) == 1 else
-                                4 * B2 * chunks(k1 % B)) for k1 in starts))
-            multi2 = [k1 for k1 in starts if chunks(k1 % B) > 1]
+                4 * (k1 % B) + (8 * B2 + base(k1) if chunks(k1 % B, B2) == 1 else
+                                4 * B2 * chunks(k1 % B, B2)) for k1 in starts))
+            multi2 = [k1 for k1 in starts if chunks(k1 % B, B2) > 1]
             if multi2:
-                work["sub_reduce"] = ("hbm", P * sum(B2 * (4 * chunks(k1 % B) + 8) + base(k1)
+                work["sub_reduce"] = ("hbm", P * sum(B2 * (4 * chunks(k1 % B, B2) + 8) + base(k1)
                                                      for k1 in multi2))
     return work
 

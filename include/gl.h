@@ -105,7 +105,7 @@ typedef struct gl_options {
     int64_t short_L;    /* short-memory window in steps, >= 0 */
     int32_t adapt_a;    /* adaptive base interval [0, a], a >= 2 */
     int32_t sum_path;   /* GL_SUM_* */
-    int32_t block_B;    /* Toeplitz block length: 0 (default 256) or 16, 32, 64, 128, 256 */
+    int32_t block_B;    /* Toeplitz block length: 0 (default 256) or 32, 64, 128, 256, 512 */
     int32_t check_finite; /* nonzero: gl_step_n fails with GL_ENONFINITE on NaN/Inf state */
     int64_t max_steps;  /* history capacity in steps, >= 1 */
     int64_t ckpt_every; /* adjoint: recompute segment length C (0 = default 500) */
@@ -161,11 +161,12 @@ gl_status gl_reset(gl_ctx *ctx, const double *u0);
 #define GL_KERNEL_HIST_GEMV 0    /* plain history sum (one launch per step and problem) */
 #define GL_KERNEL_UPDATE 1       /* stencil + reaction update */
 #define GL_KERNEL_TOEPLITZ 2     /* Toeplitz-weight x history product (one launch per block) */
-#define GL_KERNEL_TRIANGLE 3     /* one step inside a block of the blocked path (rows in the
-                                    block, stencil, update: one launch per step) */
-#define GL_KERNEL_OLD_REDUCE 4   /* FP64 sum of the Toeplitz product's history chunks */
+#define GL_KERNEL_TRIANGLE 3     /* steps inside a sub-block of the blocked path (its rows,
+                                    stencil, update: up to eight steps per launch) */
+#define GL_KERNEL_OLD_REDUCE 4   /* FP64 sum of the Toeplitz product's history chunks (only
+                                    for products cut into more than one chunk) */
 #define GL_KERNEL_SUBBLOCK 5     /* Toeplitz product over a block's rows before a sub-block */
-#define GL_KERNEL_SUB_REDUCE 6   /* FP64 sum of the sub-block product's chunks */
+#define GL_KERNEL_SUB_REDUCE 6   /* FP64 sum of the sub-block product's chunks (likewise) */
 #define GL_KERNEL_COUNT 7
 
 /* on != 0: gl_step_n brackets each launch of the timed kernels with HIP

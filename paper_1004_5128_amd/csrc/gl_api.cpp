@@ -25,7 +25,9 @@ struct gl_ctx {
     gl::Run *d_runs = nullptr;
     double *partial = nullptr;  // kMaxSplits x max P (FP64)
     int *d_flag = nullptr;
-    float *tpart = nullptr;  // Toeplitz product chunks: max chunks x B x max P (FP32)
+    float *tpart = nullptr;  // Toeplitz product chunks: max chunks x B x P (FP32)
+    int64_t tpart_len = 0;   // its length in floats
+    int ncu = 0;             // compute units of the device
     gl::BatchEntry *d_batch = nullptr;  // one entry per problem (batched plain-path launches)
 
     double *bpartial = nullptr;          // per-problem GEMV partial regions of the batch
@@ -125,8 +127,8 @@ gl_status validate(const gl_problem *probs, int32_t nprob, const gl_options *opt
         return fail(nullptr, GL_EINVAL, "gl_init: max_steps must be in [1, 2^30]");
     if (opt->ckpt_every < 0) return fail(nullptr, GL_EINVAL, "gl_init: ckpt_every must be >= 0");
     if (opt->block_B != 0 && opt->block_B != 32 && opt->block_B != 64 && opt->block_B != 128 &&
-        opt->block_B != 256)
-        return fail(nullptr, GL_EINVAL, "gl_init: block_B must be 0, 32, 64, 128 or 256");
+        opt->block_B != 256 && opt->block_B != 512)
+        return fail(nullptr, GL_EINVAL, "gl_init: block_B must be 0, 32, 64, 128, 256 or 512");
     if (opt->sum_path == GL_SUM_TOEPLITZ_BF16X3 && opt->mem_mode != GL_MEM_FULL)
         return fail(nullptr, GL_EUNSUPPORTED,
                     "gl_init: the Toeplitz path sums full memory only (mem_mode must be FULL)");
@@ -156,6 +158,38 @@ gl_status validate(const gl_problem *probs, int32_t nprob, const gl_options *opt
     return GL_OK;
 }
 
+// A tuning variable's value, or nullptr when it is unset or empty.
+const char *env_value(const char *name) {
+    const char *v = std::getenv(name);
+    return v && *v ? v : nullptr;
+}
+
+// History rows per chunk of a Toeplitz product over `rows` rows (a multiple of the K step):
+// the fixed GL_TOEPLITZ_KCHUNK length if set, else the fewest chunks for which the column
+// tiles x chunks fill the GPU (two workgroups per CU, one for the 512-row block).  Fewer
+// chunks mean fewer FP32 partial products to write and sum; the accumulation error is set by
+// the BF16 split, not by the FP32 sums over a chunk.
+int64_t chunk_cap(const gl_ctx *ctx, int BM, int64_t P, int64_t rows) {
+    const int64_t tiles = (P + 127) / 128;
+    const int64_t target = (int64_t)std::max(ctx->ncu, 1) * (BM >= 512 ? 1 : 2);
+    const int64_t nchunk = std::max<int64_t>(1, (target + tiles - 1) / tiles);
+    return std::max<int64_t>(1, std::min(nchunk, (rows + gl::kMaxTK - 1) / gl::kMaxTK));
+}
+
+int64_t chunk_rows(const gl_ctx *ctx, int BM, int64_t P, int64_t rows) {
+    if (ctx->tune.kchunk > 0) return ctx->tune.kchunk;
+    const int64_t kc = (std::max<int64_t>(rows, 1) + chunk_cap(ctx, BM, P, rows) - 1) /
+                       chunk_cap(ctx, BM, P, rows);
+    return (kc + gl::kMaxTK - 1) / gl::kMaxTK * gl::kMaxTK;
+}
+
+// Most chunks any product over at most `rows` rows is cut into (sizes the chunk buffer):
+// rows / chunk_rows <= chunk_cap, which does not decrease with rows.
+int64_t max_chunks(const gl_ctx *ctx, int BM, int64_t P, int64_t rows) {
+    if (ctx->tune.kchunk > 0) return gl::toeplitz_chunks(rows, ctx->tune.kchunk);
+    return chunk_cap(ctx, BM, P, rows);
+}
+
 gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const double *u0) {
     const gl_options &opt = ctx->opt;
     const int64_t rows = opt.max_steps + 1;
@@ -171,7 +205,9 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     // table entries cover psi(-kPsiPad .. npsi + 63): a K step stages up to 8 words past the
     // last index it uses
     const int64_t tab_len = (npsi + gl::kPsiPad + 128 + 7) / 8 * 8;
-    const int nchunk_max = gl::toeplitz_chunks(opt.max_steps, ctx->tune.kchunk);
+    int dev = 0;
+    HIP_TRY(ctx, hipGetDevice(&dev));
+    HIP_TRY(ctx, hipDeviceGetAttribute(&ctx->ncu, hipDeviceAttributeMultiprocessorCount, dev));
 
     // capacity: history arena + tables + state
     size_t need = 0;
@@ -197,7 +233,16 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     const int64_t nsnap = opt.max_steps / ctx->C + 1;
     for (const gl::Problem &pb : ctx->probs) need += (size_t)nsnap * pb.P * sizeof(double);
     need += 2 * (size_t)gl::kMaxSplits * ctx->total_points * sizeof(double);  // partials (bound)
-    if (toep) need += (size_t)nchunk_max * ctx->B * maxP * sizeof(float);
+    // FP32 chunk products: the largest chunks x B x P over the problems
+    // (a sub-block product needs at most ceil(rows / 128) <= B / 128 chunks of B2 <= 128 rows
+    // of sums, so a block product's B rows of one chunk cover it)
+    int64_t tpart_len = 0;
+    if (toep)
+        for (const gl::Problem &pb : ctx->probs)
+            tpart_len = std::max(tpart_len,
+                                 max_chunks(ctx, ctx->B, pb.P, opt.max_steps) * ctx->B * pb.P);
+    ctx->tpart_len = tpart_len;
+    need += (size_t)tpart_len * sizeof(float);
     size_t free_b = 0, total_b = 0;
     HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
     if (need + (size_t)(256u << 20) > free_b)
@@ -226,7 +271,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     if ((st = dev_alloc(ctx, &ctx->partial, (size_t)gl::kMaxSplits * maxP))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_flag, 1))) return st;
 
-    if (toep && (st = dev_alloc(ctx, &ctx->tpart, (size_t)std::max(nchunk_max, 1) * ctx->B * maxP)))
+    if (toep && (st = dev_alloc(ctx, &ctx->tpart, (size_t)std::max<int64_t>(tpart_len, 1))))
         return st;
 
 
@@ -399,10 +444,14 @@ gl_status step_gemv(gl_ctx *ctx) {
 gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int BM,
                      int64_t k_out, int64_t j_lo, int64_t j_hi, double *out, const double *base,
                      int gemm_id, int reduce_id) {
-    const int nchunk = gl::toeplitz_chunks(j_hi - j_lo, ctx->tune.kchunk);
+    const int64_t kchunk = chunk_rows(ctx, BM, pb.P, j_hi - j_lo);
+    const int nchunk = gl::toeplitz_chunks(j_hi - j_lo, kchunk);
+    if (nchunk > 1 && (int64_t)nchunk * BM * pb.P > ctx->tpart_len)
+        return fail(ctx, GL_EINVAL, "internal: %d chunk products of %d x %lld exceed the buffer",
+                    nchunk, BM, (long long)pb.P);
     gl_status st = timed(ctx, gemm_id, [&] {
         gl::launch_toeplitz_gemm(BM, hist, ld, pb.P, pb.psi_tab, pb.tab_len, k_out, j_lo, j_hi,
-                                 ctx->tune.kchunk, ctx->tpart, out, base, ctx->stream);
+                                 kchunk, ctx->tpart, out, base, ctx->stream);
     });
     if (st != GL_OK || nchunk <= 1) return st;
     return timed(ctx, reduce_id, [&] {
@@ -635,13 +684,13 @@ gl_status gl_init(const gl_problem *probs, int32_t nprob, const gl_options *opt,
     if (st != GL_OK) return st;
     std::unique_ptr<gl_ctx> ctx(new gl_ctx);
     ctx->opt = *opt;
-    if (const char *v = std::getenv("GL_GEMV_GROUPS")) ctx->tune.gemv_groups = std::max(1L, std::atol(v));
-    if (const char *v = std::getenv("GL_GEMV_SERPENTINE")) ctx->tune.serpentine = std::atoi(v) != 0;
-    if (const char *v = std::getenv("GL_SUBBLOCK")) ctx->tune.sub_B = std::atol(v);
-    if (const char *v = std::getenv("GL_FUSE"))
+    if (const char *v = env_value("GL_GEMV_GROUPS")) ctx->tune.gemv_groups = std::max(1L, std::atol(v));
+    if (const char *v = env_value("GL_GEMV_SERPENTINE")) ctx->tune.serpentine = std::atoi(v) != 0;
+    if (const char *v = env_value("GL_SUBBLOCK")) ctx->tune.sub_B = std::atol(v);
+    if (const char *v = env_value("GL_FUSE"))
         ctx->tune.fuse = std::min<int64_t>(gl::kMaxFuse, std::max(1L, std::atol(v)));
-    if (const char *v = std::getenv("GL_TOEPLITZ_KCHUNK"))
-        ctx->tune.kchunk = std::max(64L, std::atol(v) / 64 * 64);
+    if (const char *v = env_value("GL_TOEPLITZ_KCHUNK"))
+        ctx->tune.kchunk = std::max<int64_t>(gl::kMaxTK, std::atol(v) / gl::kMaxTK * gl::kMaxTK);
     ctx->stream = static_cast<hipStream_t>(opt->stream);
     st = init_impl(ctx.get(), probs, nprob, u0);
     if (st != GL_OK) {

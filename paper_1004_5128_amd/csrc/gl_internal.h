@@ -129,14 +129,16 @@ void launch_update_batched(const BatchEntry *tab, int nprob, int64_t wgs, int64_
 struct Tuning {
     int64_t gemv_groups = 1024;  // target workgroups per GEMV launch
     bool serpentine = false;     // alternate the traversal direction every step
-    int64_t kchunk = 8192;       // history rows per Toeplitz product chunk (multiple of 64)
+    int64_t kchunk = 0;          // history rows per Toeplitz product chunk (multiple of 128);
+                                 // 0: per product, the fewest chunks that fill the GPU
     int64_t sub_B = 32;          // sub-block length of the blocked path (32 or 64; 0: off)
     int64_t fuse = 8;            // in-block steps per launch (1 .. kMaxFuse)
 };
 
 // ---- blocked Toeplitz path
-constexpr int kPsiPad = 64;   // zero entries before psi(0) in the BF16 weight tables
-constexpr int kMaxBlock = 256;
+constexpr int kPsiPad = 128;  // zero entries before psi(0) in the BF16 weight tables
+constexpr int kMaxBlock = 512;
+constexpr int kMaxTK = 128;   // history rows per Toeplitz K step, at most (chunks are multiples)
 
 // BF16 hi/lo weight tables (8 shifted copies each) from the FP64 weights psi[0..npsi).
 void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_t *tab,

@@ -27,6 +27,7 @@ namespace gl {
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x4v_t __attribute__((ext_vector_type(4)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
@@ -85,29 +86,39 @@ void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_
 // k = 8(l/32)..+7; B lane l holds column l%32, the same k; the accumulator
 // lane l holds column l%32, rows 8(r/4) + 4(l/32) + r%4 for r = 0..15.
 
-constexpr int kTN = 128;              // points per workgroup
-constexpr int kTK = 64;               // history rows per K step
-constexpr int kLdsRow = kTK / 8 + 1;  // 16-byte words per point in LDS (one pad word)
+constexpr int kTN = 128;  // points per workgroup
 
-// Weight words one K step reads from each of the 16 tables (hi/lo x 8 shifts): the
-// table indices of a step span BM + 63 entries starting at k0 - jt + 1.
+// Per block length: workgroup size (4 waves, 8 for the 512-row block, which then shares each
+// history tile between twice as many output rows), history rows per K step (each lane loads
+// 8 rows x 4 points per step), 16-byte LDS words per point (one pad word, odd: conflict-free).
+template <int BM> constexpr int gemm_threads() { return BM >= 512 ? 512 : 256; }
+template <int BM> constexpr int gemm_tk() { return gemm_threads<BM>() / 4; }
+template <int BM> constexpr int gemm_lds_row() { return gemm_tk<BM>() / 8 + 1; }
+
+// Weight words one K step reads from each of the 16 tables (hi/lo x 8 shifts): the table
+// indices of a step span BM + TK - 1 entries starting at k0 - jt - (TK - 1) + kPsiPad.
 template <int BM>
 constexpr int psi_words() {
-    return (BM + 63 + 7) / 8 + 2;
+    return (BM + gemm_tk<BM>() + 6) / 8 + 2;
 }
 
 template <int BM>
-__global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
+__global__ __launch_bounds__(gemm_threads<BM>(), BM >= 512 ? 1 : 2) void toeplitz_gemm_kernel(
     const float *__restrict__ H, int64_t ld, int64_t P, const u32x4_t *__restrict__ tab,
     int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
     float *__restrict__ out, double *__restrict__ direct, const double *__restrict__ base) {
-    constexpr int WM = BM >= 128 ? 4 : BM / 32;  // waves along the block rows
-    constexpr int WN = 4 / WM;                   // waves along the points
-    constexpr int RB = BM / 32 / WM;             // 32-row blocks per wave
-    constexpr int CB = kTN / 32 / WN;            // 32-point blocks per wave
+    constexpr int kThreads = gemm_threads<BM>();
+    constexpr int kTK = gemm_tk<BM>();
+    constexpr int kLdsRow = gemm_lds_row<BM>();
+    constexpr int kWaves = kThreads / 64;
+    constexpr int WM = BM / 32 >= kWaves ? kWaves : BM / 32;  // waves along the block rows
+    constexpr int WN = kWaves / WM;                             // waves along the points
+    constexpr int RB = BM / 32 / WM;                            // 32-row blocks per wave
+    constexpr int CB = kTN / 32 / WN;                           // 32-point blocks per wave
     constexpr int NW = psi_words<BM>();
     constexpr int NPSI = 16 * NW;                         // weight words staged per K step
-    constexpr int PSI_PER_LANE = (NPSI + 255) / 256;
+    constexpr int PSI_PER_LANE = (NPSI + kThreads - 1) / kThreads;
+    static_assert(kPsiPad >= kTK, "the weight tables' zero pad covers a K step");
     __shared__ u32x4_t lhi[kTN * kLdsRow];
     __shared__ u32x4_t llo[kTN * kLdsRow];
     __shared__ u32x4_t lpsi[NPSI];                        // [table 0..15][NW words]
@@ -122,7 +133,7 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
     const int64_t j_end = j_begin + kchunk < j_hi ? j_begin + kchunk : j_hi;
     const int64_t tab_words = tab_len / 8;  // 16-byte words per table
 
-    // loader: 32 groups of 4 points x 8 groups of 8 rows
+    // loader: 32 groups of 4 points x kTK / 8 groups of 8 rows
     const int ng = tid & 31, kg = tid >> 5;
     const int64_t col = n0 + ng * 4;
     const bool col_ok = col < P;  // P <= ld, ld % 4 == 0: the 16-byte load stays in the row
@@ -154,23 +165,24 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
         }
     }
 
-    float4 pre[8];
+    f32x4v_t pre[8];
     u32x4_t ppre[PSI_PER_LANE];
-    // first weight word of a K step: word of table index k0 - jt + 1, less one for slack
-    auto psi_w0 = [&](int64_t jt) { return (k0 - jt + 1) / 8 - 1; };
+    // first weight word of a K step: word of its lowest table index, less one for slack
+    auto psi_w0 = [&](int64_t jt) { return (k0 - jt - (kTK - 1) + kPsiPad) / 8 - 1; };
     auto load_tile = [&](int64_t jt) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const int64_t row = jt + kg * 8 + e;
-            pre[e] = (col_ok && row < j_end) ? *reinterpret_cast<const float4 *>(H + row * ld + col)
-                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            pre[e] = (col_ok && row < j_end)
+                         ? *reinterpret_cast<const f32x4v_t *>(H + row * ld + col)
+                         : f32x4v_t{};
         }
     };
     auto load_psi = [&](int64_t jt) {
         const int64_t w0 = psi_w0(jt);
 #pragma unroll
         for (int i = 0; i < PSI_PER_LANE; ++i) {
-            const int idx = tid + i * 256;
+            const int idx = tid + i * kThreads;
             if (idx < NPSI) ppre[i] = tab[(int64_t)(idx / NW) * tab_words + w0 + idx % NW];
         }
     };
@@ -179,8 +191,7 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
         for (int c = 0; c < 4; ++c) {
             float v[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                v[e] = c == 0 ? pre[e].x : c == 1 ? pre[e].y : c == 2 ? pre[e].z : pre[e].w;
+            for (int e = 0; e < 8; ++e) v[e] = pre[e][c];
             // element p of the group holds row 7 - p: word w packs rows 7 - 2w (low half) and
             // 6 - 2w; hi rounded to nearest even by the packed conversion, lo the same of the
             // (exact) remainder
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
         }
 #pragma unroll
         for (int i = 0; i < PSI_PER_LANE; ++i) {
-            const int idx = tid + i * 256;
+            const int idx = tid + i * kThreads;
             if (idx < NPSI) lpsi[idx] = ppre[i];
         }
     };
@@ -217,9 +228,10 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
 #pragma unroll
         for (int q = 0; q < kTK / 16; ++q) {
             // A operands of this 16-row step for the wave's row blocks: weights of rows
-            // jt+16q+8g+7-p, p = 0..7, i.e. psi(mstart + p), from the staged table slice
+            // jt+16q+8g+7-p, p = 0..7, i.e. psi(mstart + p), from the staged table slice;
+            // B operands for all its point blocks; then the three products per accumulator
             const int64_t w0 = psi_w0(jt);
-            bf16x8_t Ah[RB], Al[RB];
+            bf16x8_t Ah[RB], Al[RB], Bh[CB], Bl[CB];
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
                 const int b = (wm * RB + i) * 32 + (lane & 31);
@@ -229,19 +241,20 @@ __global__ __launch_bounds__(256, 2) void toeplitz_gemm_kernel(
                 Ah[i] = __builtin_bit_cast(bf16x8_t, lpsi[s * NW + w]);
                 Al[i] = __builtin_bit_cast(bf16x8_t, lpsi[(8 + s) * NW + w]);
             }
-            // B operands one 32-point block at a time (fewer live registers)
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
                 const int n = (wn * CB + j) * 32 + (lane & 31);
-                const bf16x8_t Bh = __builtin_bit_cast(bf16x8_t, lhi[n * kLdsRow + 2 * q + g]);
-                const bf16x8_t Bl = __builtin_bit_cast(bf16x8_t, llo[n * kLdsRow + 2 * q + g]);
+                Bh[j] = __builtin_bit_cast(bf16x8_t, lhi[n * kLdsRow + 2 * q + g]);
+                Bl[j] = __builtin_bit_cast(bf16x8_t, llo[n * kLdsRow + 2 * q + g]);
+            }
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
 #pragma unroll
                 for (int i = 0; i < RB; ++i) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[i], Bh, acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[i], Bl, acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[i], Bh, acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Al[i], Bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[i], Bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ah[i], Bh[j], acc[i][j], 0, 0, 0);
                 }
-            }
         }
         // the next step's weights: in flight across the barrier, not held during the MFMAs
         if (more) load_psi(jt + kTK);
@@ -298,33 +311,30 @@ void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const u
                           float *out, double *direct, const double *base, hipStream_t s) {
     const int nchunk = toeplitz_chunks(j_hi - j_lo, kchunk);
     if (nchunk == 0) return;
-    // K steps start 64-row aligned from j_lo; with k0 and j_lo multiples of 32 every step
-    // has k0 - jt >= 32, which keeps the staged weight words inside the tables
-    if (k0 % 32 != 0 || j_lo % 32 != 0 || j_hi > k0 || kchunk % kTK != 0) return;
+    // K steps start at j_lo; with k0 and j_lo multiples of 32 every step has k0 - jt >= 32,
+    // which (with the zero pad of kPsiPad >= TK entries) keeps the staged weight words inside
+    // the tables
+    if (k0 % 32 != 0 || j_lo % 32 != 0 || j_hi > k0 || kchunk % kMaxTK != 0) return;
     if (nchunk > 1) direct = nullptr;  // the chunk reduction writes the sums
     dim3 grid((unsigned)((P + kTN - 1) / kTN), (unsigned)nchunk);
     const u32x4_t *t = reinterpret_cast<const u32x4_t *>(tab);
+#define GL_GEMM_CASE(bm)                                                                       \
+    case bm:                                                                                   \
+        GL_LAUNCH(toeplitz_gemm_kernel<bm>, grid, dim3(gemm_threads<bm>()), 0, s, H, ld, P, t,  \
+                  tab_len, k0, j_lo, j_hi, kchunk, out, direct, base);                          \
+        break;
     switch (BM) {
-        case 32:
-            GL_LAUNCH(toeplitz_gemm_kernel<32>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
-                      j_lo, j_hi, kchunk, out, direct, base);
-            break;
-        case 64:
-            GL_LAUNCH(toeplitz_gemm_kernel<64>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
-                      j_lo, j_hi, kchunk, out, direct, base);
-            break;
-        case 128:
-            GL_LAUNCH(toeplitz_gemm_kernel<128>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
-                      j_lo, j_hi, kchunk, out, direct, base);
-            break;
+        GL_GEMM_CASE(32)
+        GL_GEMM_CASE(64)
+        GL_GEMM_CASE(128)
+        GL_GEMM_CASE(256)
+        GL_GEMM_CASE(512)
         default:
-            GL_LAUNCH(toeplitz_gemm_kernel<256>, grid, dim3(256), 0, s, H, ld, P, t, tab_len, k0,
-                      j_lo, j_hi, kchunk, out, direct, base);
             break;
     }
+#undef GL_GEMM_CASE
 }
 
-// Old[b * P + p] = sum over chunks c (in order) of part[(c * BM + b) * P + p], FP64.
 __global__ void old_reduce_kernel(const float *__restrict__ part, int nchunk, int64_t BP,
                                   double *__restrict__ old, const double *__restrict__ base) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -2,6 +2,8 @@
 one BF16 hi/lo x 3 matrix product with FP32 accumulation, FP64 chunk sums; each step
 inside a sub-block up to eight per kernel) with the FP64 oracle.  Tolerance: relative
 L2 <= 1e-5."""
+import contextlib
+
 import numpy as np
 import pytest
 import torch
@@ -15,7 +17,7 @@ pytestmark = pytest.mark.gpu
 TOL_MFMA = 1e-5
 
 
-@pytest.mark.parametrize("B", [32, 64, 128, 256])
+@pytest.mark.parametrize("B", [32, 64, 128, 256, 512])
 @pytest.mark.parametrize("P", [1, 129, 1000, 4097])
 def test_block_history_sum_matches_oracle(B, P):
     # One history sum at several positions relative to the block boundaries, over a seeded
@@ -38,6 +40,29 @@ def test_block_history_sum_matches_oracle(B, P):
             got = s.history_sum(k, Hd).cpu().numpy()
             ref = oracle.history_sum(gamma, mem, k, H[:, :P])
             scale = np.sum(np.abs(psi[:k + 1]))   # sum |psi(m) H[k-m]| <= scale * max|H|
+            assert np.abs(got - ref).max() <= TOL_MFMA * scale, (k, np.abs(got - ref).max())
+
+
+@pytest.mark.parametrize("kchunk", ["128", "1024", "4096", None])
+def test_chunk_lengths_agree_with_oracle(kchunk):
+    # the history dimension of each block product cut into chunks of 128, 1024 or 4096 rows
+    # (FP32 chunk products summed in FP64 by a second kernel) or, by default, into the fewest
+    # chunks that fill the GPU (one here: the product kernel writes the FP64 sums itself)
+    gamma, kmax, P = 0.7, 5000, 65536
+    print_case("toeplitz chunks", kchunk)
+    rng = np.random.default_rng(11)
+    cols = rng.choice(P, 512, replace=False)
+    H = rng.uniform(-0.1, 0.1, (kmax + 1, P)).astype(np.float32)
+    Hd = torch.as_tensor(H).cuda()
+    p = W.problem(1, P, gamma, 1.0, 0.05)
+    mem = W.memory("full")
+    psi = oracle.psi(gamma, kmax)
+    ctx = env("GL_TOEPLITZ_KCHUNK", kchunk) if kchunk else contextlib.nullcontext()
+    with ctx, gl().Solver(p, mem, np.zeros(P), max_steps=kmax, sum_path="toeplitz") as s:
+        for k in (4865, kmax):
+            got = s.history_sum(k, Hd).cpu().numpy()[cols]
+            ref = oracle.history_sum(gamma, mem, k, np.ascontiguousarray(H[:, cols]))
+            scale = 0.1 * np.sum(np.abs(psi[:k + 1]))
             assert np.abs(got - ref).max() <= TOL_MFMA * scale, (k, np.abs(got - ref).max())
 
 
@@ -69,7 +94,7 @@ def test_cfg1_toeplitz_matches_oracle():
     assert rel_l2(got, ref) <= TOL_MFMA
 
 
-@pytest.mark.parametrize("B", [32, 64, 128, 256])
+@pytest.mark.parametrize("B", [32, 64, 128, 256, 512])
 def test_2d_reduced_cfg2_toeplitz_matches_oracle(B):
     w = W.cfg2(n=64, nsteps=1100)
     print_case(w["name"], "toeplitz", B)
@@ -108,7 +133,7 @@ def test_split_calls_equal_one_call():
 
 @pytest.mark.parametrize("dims,B,sub", [((2, 37, 23), 64, 32), ((2, 48, 48), 256, 32),
                                          ((1, 600, 1), 32, 32), ((2, 20, 17), 128, 0),
-                                         ((1, 300, 1), 256, 64)])
+                                         ((1, 300, 1), 256, 64), ((2, 24, 24), 512, 32)])
 def test_fused_steps_do_not_depend_on_grouping(dims, B, sub):
     # the in-block steps taken 1, 3 or 8 per launch, and the run cut into calls of odd
     # lengths, give the same bits: each step's sum is one chain that does not depend on
