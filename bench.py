@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix, TFLOP/s
-PREFIX_STEPS = 800           # oracle sample: the first 800 steps of the workload
+PREFIX_STEPS = 1200           # oracle sample: the first 800 steps of the workload
 MODES = [(1, 1), (1, 3), (3, 1), (3, 3), (1, 5), (5, 5)]
 
 
@@ -67,6 +67,7 @@ def source_sha(kernel):
 
 KERNEL_SOURCES = {"hist_gemv": "gl_kernels.hip", "update": "gl_kernels.hip",
                   "toeplitz": "gl_toeplitz.hip", "old_reduce": "gl_toeplitz.hip",
+                  "subblock": "gl_toeplitz.hip", "sub_reduce": "gl_toeplitz.hip",
                   "triangle": "gl_block.hip"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.txt")
 
@@ -85,12 +86,30 @@ def measured_traffic():
     return out
 
 
-ROCPROF_NAMES = {"gl::hist_gemv_kernel": "hist_gemv", "gl::update_kernel": "update",
-                 "gl::toeplitz_gemm_kernel": "toeplitz", "gl::old_reduce_kernel": "old_reduce",
-                 "gl::block_step_kernel": "triangle"}
+def rocprof_name(kernel, B, B2):
+    """The bench's name of a libgl kernel in a rocprofv3 record (the Toeplitz product kernel
+    is the block product for B output rows and the sub-block product for B2), or None."""
+    k = kernel.replace("void ", "")
+    if k.startswith("gl::hist_gemv_kernel") or k.startswith("gl::hist_gemv_batched_kernel"):
+        return "hist_gemv"
+    if k.startswith("gl::update_kernel") or k.startswith("gl::update_batched_kernel"):
+        return "update"
+    if k.startswith("gl::toeplitz_gemm_kernel<%d>" % B):
+        return "toeplitz"
+    if B2 and k.startswith("gl::toeplitz_gemm_kernel<%d>" % B2):
+        return "subblock"
+    if k.startswith("gl::old_reduce_kernel"):
+        return "old_reduce"
+    if k.startswith("gl::block_steps_kernel"):
+        return "triangle"
+    return None
 
 
-def summarize_counters(fetch_csv, write_csv, work):
+# solves of each path in a --profile-steps run: the timed solve and the profiled one
+PROFILE_SOLVES = 2
+
+
+def summarize_counters(fetch_csv, write_csv, work, B):
     """Lines of the traffic summary from two rocprofv3 counter CSVs (FETCH_SIZE, WRITE_SIZE, KiB
     per dispatch) of a --profile-steps run with --copy-calibration; `work` is that run's
     algorithmic work.  Each counter is scaled by what it reads for the 1 GiB device copy."""
@@ -105,9 +124,9 @@ def summarize_counters(fetch_csv, write_csv, work):
             v = float(row["Counter_Value"])
             if "copyBuffer" in row["Kernel_Name"] and int(row["Grid_Size"]) >= 131072:
                 copies.append(v)
-            for prefix, name in ROCPROF_NAMES.items():
-                if prefix in row["Kernel_Name"].replace("void ", ""):
-                    vals[name].append(v)
+            name = rocprof_name(row["Kernel_Name"], B, sub_block(B))
+            if name:
+                vals[name].append(v)
         return vals, copies
 
     fetch, fcopy = per_kernel(fetch_csv, "FETCH_SIZE")
@@ -122,7 +141,8 @@ def summarize_counters(fetch_csv, write_csv, work):
         kind, w = work.get(name + "_bytes", work.get(name, (None, None)))
         if kind != "hbm":
             continue
-        alg = w / n
+        # `work` covers one solve; the counted launches span PROFILE_SOLVES solves
+        alg = w * PROFILE_SOLVES / n
         lines.append("kernel=%s source_sha=%s launches=%d fetch_kib_per_launch=%.1f "
                      "write_kib_per_launch=%.1f hbm_bytes_per_launch=%.0f "
                      "algorithmic_bytes_per_launch=%.0f traffic_over_algorithmic=%.4f"
@@ -137,6 +157,14 @@ def sub_block(B):
     return B2 if 0 < B2 < B and B % B2 == 0 else 0
 
 
+def compute_units():
+    """Compute units of GPU 0 (MI355X: 256 when summarizing counters without a GPU)."""
+    import torch
+    if torch.cuda.is_available():
+        return torch.cuda.get_device_properties(0).multi_processor_count
+    return 256
+
+
 def toeplitz_chunks(rows, BM, P):
     """Chunks of a Toeplitz product over `rows` history rows, as the library cuts it: rows of
     GL_TOEPLITZ_KCHUNK if set, else the fewest chunks whose workgroups (128-point column
@@ -145,9 +173,8 @@ def toeplitz_chunks(rows, BM, P):
     if v:
         kc = max(128, int(v) // 128 * 128)
     else:
-        import torch
-        ncu = torch.cuda.get_device_properties(0).multi_processor_count
         tiles = -(-P // 128)
+        ncu = compute_units()
         target = ncu * (1 if BM >= 512 else 2)
         n = max(1, min(-(-target // tiles), -(-rows // 128)))
         kc = -(-(-(-max(rows, 1) // n)) // 128) * 128
@@ -306,7 +333,8 @@ def main():
         for path in [x for x in args.paths.split(",") if x]:
             work = algorithmic_work(path, W.npoints(w["problem"]), n, args.block_B or 256,
                                     [k + 1 for k in range(n)])
-            print("\n".join(summarize_counters(*args.summarize_counters, work)))
+            print("\n".join(summarize_counters(*args.summarize_counters, work,
+                                                args.block_B or 256)))
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the solver runs on a single "

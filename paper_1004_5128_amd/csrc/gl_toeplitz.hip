@@ -77,16 +77,25 @@ void launch_psi_tables(const double *psi, int64_t npsi, int64_t tab_len, uint16_
 // The next K step's history and weight loads are issued before the current step's
 // MFMAs.
 //
-// LDS row r holds point 4 (r % 32) + r / 32 of the tile, so column c of 32-point block j is
-// point 4c + j: the transposed stores (a lane's four consecutive points go to rows 32 apart)
-// and the B reads (consecutive lanes, consecutive rows) both walk the rows with an odd word
-// stride, free of bank conflicts.
+// LDS rows are permuted inside each 32-point block (lds_row below): the transposed stores (a
+// lane's four consecutive points, 32 lanes) then hit distinct banks within every 8 and every
+// 16 lanes, as do the B reads (consecutive lanes, consecutive rows), and column c of block j
+// is point block_point(j, c): one accumulator store instruction still covers the block's 32
+// consecutive points.
 //
 // v_mfma_f32_32x32x16_bf16 lane layout (wave64): A lane l holds row l%32,
 // k = 8(l/32)..+7; B lane l holds column l%32, the same k; the accumulator
 // lane l holds column l%32, rows 8(r/4) + 4(l/32) + r%4 for r = 0..15.
 
 constexpr int kTN = 128;  // points per workgroup
+
+// LDS row of tile point p, and the tile point of column c of 32-point block j (inverses).
+__device__ __forceinline__ int lds_row(int p) {
+    return 32 * (p >> 5) + 8 * ((p & 3) ^ ((p >> 5) & 1)) + ((p & 31) >> 2);
+}
+__device__ __forceinline__ int block_point(int j, int c) {
+    return 32 * j + 4 * (c & 7) + ((c >> 3) ^ (j & 1));
+}
 
 // Per block length: workgroup size (4 waves, 8 for the 512-row block, which then shares each
 // history tile between twice as many output rows), history rows per K step (each lane loads
@@ -154,7 +163,7 @@ __global__ __launch_bounds__(gemm_threads<BM>(), BM >= 512 ? 1 : 2) void toeplit
             for (int i = 0; i < RB; ++i)
 #pragma unroll
                 for (int j = 0; j < CB; ++j) {
-                    const int64_t n = n0 + 4 * (lane & 31) + (wn * CB + j);
+                    const int64_t n = n0 + block_point(wn * CB + j, lane & 31);
 #pragma unroll
                     for (int r = 0; r < 16; ++r)
                         bpre[i][j][r] =
@@ -204,9 +213,8 @@ __global__ __launch_bounds__(gemm_threads<BM>(), BM >= 512 ? 1 : 2) void toeplit
                 h4[w] = hb;
                 l4[w] = __builtin_bit_cast(uint32_t, __builtin_convertvector(x - hx, bf16x2_t));
             }
-            // point 4 ng + c lives in LDS row 32 c + ng (see the layout note above)
-            lhi[(c * 32 + ng) * kLdsRow + kg] = h4;
-            llo[(c * 32 + ng) * kLdsRow + kg] = l4;
+            lhi[lds_row(4 * ng + c) * kLdsRow + kg] = h4;
+            llo[lds_row(4 * ng + c) * kLdsRow + kg] = l4;
         }
 #pragma unroll
         for (int i = 0; i < PSI_PER_LANE; ++i) {
@@ -266,7 +274,7 @@ __global__ __launch_bounds__(gemm_threads<BM>(), BM >= 512 ? 1 : 2) void toeplit
         for (int i = 0; i < RB; ++i)
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
-                const int64_t n = n0 + 4 * (lane & 31) + (wn * CB + j);
+                const int64_t n = n0 + block_point(wn * CB + j, lane & 31);
                 if (n < P) {
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
@@ -291,7 +299,7 @@ __global__ __launch_bounds__(gemm_threads<BM>(), BM >= 512 ? 1 : 2) void toeplit
     for (int i = 0; i < RB; ++i)
 #pragma unroll
         for (int j = 0; j < CB; ++j) {
-            const int64_t n = n0 + 4 * (lane & 31) + (wn * CB + j);
+            const int64_t n = n0 + block_point(wn * CB + j, lane & 31);
             if (n < P) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
