@@ -308,6 +308,49 @@ def roofline_of(kind, work_per_solve, launches_per_solve, ms_per_solve):
             "algorithmic_bytes_per_launch": per_launch, "avg_launch_us": avg_s * 1e6}
 
 
+def probe_product(k, reps=3):
+    """The block product alone: gl_history_sum at step k (B = 256, so the product covers the
+    k0 = k - k % 256 rows before the block, plus a short GEMV) over a synthetic FP32 history
+    of 65536 points, timed `reps` times; for counter collection on the product kernel."""
+    import torch
+    from paper_1004_5128_amd import gl, workloads as W
+    P = 65536
+    gen = torch.Generator(device="cuda").manual_seed(5)
+    H = torch.rand((k + 1, P), dtype=torch.float32, device="cuda", generator=gen) * 0.1
+    p = W.problem(1, P, 0.8, 1.0, 0.05)
+    out = []
+    with gl.Solver(p, W.memory("full"), np.zeros(P), max_steps=k, sum_path="toeplitz") as s:
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.history_sum(k, H)
+            torch.cuda.synchronize()
+            out.append((time.perf_counter() - t0) * 1e3)
+    print(json.dumps({"probe": "toeplitz product", "k": k, "points": P, "ms": out}), flush=True)
+
+
+def probe_hipblaslt(reps=10):
+    """Vendor BF16 GEMMs (torch.matmul -> hipBLASLt) on the same GPU for comparison: square
+    4096..16384 and the block product's shape (256 x 19968) x (19968 x 65536)."""
+    import torch
+    res = {}
+    for m, kk, n in ((4096, 4096, 4096), (8192, 8192, 8192), (16384, 16384, 16384),
+                     (256, 19968, 65536)):
+        a = torch.randn(m, kk, dtype=torch.bfloat16, device="cuda")
+        b = torch.randn(kk, n, dtype=torch.bfloat16, device="cuda")
+        for _ in range(2):
+            c = a @ b
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c = a @ b
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        res["%dx%dx%d" % (m, kk, n)] = {"ms": dt * 1e3, "tflops": 2 * m * kk * n / dt / 1e12}
+        del a, b, c
+    print(json.dumps({"probe": "hipblaslt bf16", "gemms": res}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,7 +368,19 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the traffic summary lines from the counter CSVs of a "
                          "--profile-steps run of the given --paths (no GPU)")
+    ap.add_argument("--probe-product", type=int, default=0, metavar="K",
+                    help="time the block product alone at step K (for counter collection)")
+    ap.add_argument("--probe-hipblaslt", action="store_true",
+                    help="time vendor BF16 GEMMs (torch.matmul) for comparison")
     args = ap.parse_args()
+    if args.probe_product or args.probe_hipblaslt:
+        import torch
+        torch.cuda.set_device(0)
+        if args.probe_product:
+            probe_product(args.probe_product)
+        if args.probe_hipblaslt:
+            probe_hipblaslt()
+        return
     if args.summarize_counters:
         from paper_1004_5128_amd import workloads as W
         w = W.cfg2()
