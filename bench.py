@@ -293,6 +293,50 @@ def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
             "u_prefix": u_prefix, "steps": 1}
 
 
+MODE_RUNS = (("short_L1000", {"mode": "short", "L": 1000}), ("adaptive_a2", {"mode": "adaptive", "a": 2}),
+             ("adaptive_a4", {"mode": "adaptive", "a": 4}), ("adaptive_a10", {"mode": "adaptive", "a": 10}))
+
+
+def run_memory_modes(w, u_full, oracle_modes):
+    """The same workload under short memory (L = 1000 steps) and adaptive memory (a = 2, 4, 10,
+    partition reading) on the plain path: time per solve (one warmup, one timed), history
+    MACs/s and algorithmic GB/s, the rel-L2 difference from the full-memory result (the
+    paper's error of a memory mode) and, with the oracle, the largest sine-mode error against
+    the oracle's recursion for that mode."""
+    import torch
+    from paper_1004_5128_amd import gl, workloads as W
+    p, n = w["problem"], w["nsteps"]
+    P = W.npoints(p)
+    u0 = torch.as_tensor(w["u0"], dtype=torch.float64).cuda()
+    out = {}
+    for name, spec in MODE_RUNS:
+        mem = W.memory(spec["mode"], **{k: v for k, v in spec.items() if k != "mode"})
+        log("memory mode", name)
+        with gl.Solver(p, mem, u0, max_steps=n) as s:
+            terms = sum(s.schedule_terms(k) for k in range(n))
+            s.advance(n)
+            torch.cuda.synchronize()
+            s.reset(u0)
+            t0 = time.perf_counter()
+            s.advance(n)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            uT = s.state().cpu().numpy()
+        d = {"ms_per_solve": dt * 1e3, "history_macs_per_solve": P * terms,
+             "history_macs_per_s": P * terms / dt,
+             "algorithmic_gbs": 4 * P * (terms - n) / dt / 1e9,
+             "rel_l2_vs_full_memory": float(np.linalg.norm(uT - u_full) / np.linalg.norm(u_full))}
+        if oracle_modes is not None:
+            import oracle
+            c0 = modal(w["u0"], p, MODES)
+            ref = np.array([c0[i] * oracle.mode_run(p, mem, a, b, 1.0, n)[-1]
+                            for i, (a, b) in enumerate(MODES)])
+            cg = modal(uT, p, MODES)
+            d["modal_err_vs_oracle"] = float(np.abs(cg - ref).max() / np.abs(ref).max())
+        out[name] = d
+    return out
+
+
 def roofline_of(kind, work_per_solve, launches_per_solve, ms_per_solve):
     """Achieved rate of one kernel: algorithmic work per launch / average launch time."""
     per_launch = work_per_solve / launches_per_solve
@@ -360,6 +404,8 @@ def main():
                     help="history-sum paths to time; the last one is the headline value")
     ap.add_argument("--block-B", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the short / adaptive memory runs of the same workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 1 GiB device copy (reference for traffic counters)")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -457,6 +503,14 @@ def main():
             d["modal_err_vs_oracle_full_length"] = float(np.abs(cg - oracle_modal).max() /
                                                          np.abs(oracle_modal).max())
         out_paths[path] = d
+
+    if not args.no_modes and not args.profile_steps:
+        full = res.get("gemv", res[primary])
+        out_paths["memory_modes"] = run_memory_modes(
+            w, full["uT"], None if args.no_cpu else True)
+        out_paths["memory_modes"]["full"] = {
+            "path": "gemv" if "gemv" in res else primary,
+            "ms_per_solve": full["ms_per_step"], "history_macs_per_solve": full["macs"]}
 
     r = res[primary]
     # the dominant kernel of the headline path (largest share of the solve's time)

@@ -198,3 +198,22 @@ def test_cfg2_sine_mode_full_size_toeplitz():
     got = gpu_run(p, w["memory"], phi, w["nsteps"], sum_path="toeplitz")
     v = oracle.mode_run(p, w["memory"], 2, 3, 1.0, w["nsteps"])
     assert rel_l2(got, v[-1] * phi) <= TOL_MFMA
+
+
+def test_cfg3_full_size_blocked_paths_agree():
+    # 512^2 Fisher-KPP, 50000 steps (a 52 GB history), the blocked path with B = 64, 128 and
+    # 256: the three full-length results agree (each within the BF16-split error of the
+    # exact sums), and the B = 256 launch configuration matches the oracle over a 520-step
+    # prefix (two block boundaries, sub-block products, fused in-block launches)
+    w = W.cfg3()
+    p, mem, n = w["problem"], w["memory"], w["nsteps"]
+    print_case(w["name"], "prefix 520")
+    pre = gpu_run(p, mem, w["u0"], 520, sum_path="toeplitz", max_steps=n)
+    assert rel_l2(pre, oracle.run(p, mem, w["u0"], 520)) <= TOL_MFMA
+    outs = {}
+    for B in (256, 128, 64):
+        print_case(w["name"], "full length", B)
+        outs[B] = gpu_run(p, mem, w["u0"], n, sum_path="toeplitz", block_B=B)
+        assert np.all(np.isfinite(outs[B]))
+    for B in (128, 64):
+        assert rel_l2(outs[B], outs[256]) <= TOL_MFMA, (B, rel_l2(outs[B], outs[256]))
