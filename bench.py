@@ -293,26 +293,29 @@ def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
             "u_prefix": u_prefix, "steps": 1}
 
 
-MODE_RUNS = (("short_L1000", {"mode": "short", "L": 1000}), ("adaptive_a2", {"mode": "adaptive", "a": 2}),
-             ("adaptive_a4", {"mode": "adaptive", "a": 4}), ("adaptive_a10", {"mode": "adaptive", "a": 10}))
+MODE_RUNS = (("short_L1000", "gemv", {"mode": "short", "L": 1000}),
+             ("short_L1000_blocked", "toeplitz", {"mode": "short", "L": 1000}),
+             ("adaptive_a2", "gemv", {"mode": "adaptive", "a": 2}),
+             ("adaptive_a4", "gemv", {"mode": "adaptive", "a": 4}),
+             ("adaptive_a10", "gemv", {"mode": "adaptive", "a": 10}))
 
 
 def run_memory_modes(w, u_full, oracle_modes):
-    """The same workload under short memory (L = 1000 steps) and adaptive memory (a = 2, 4, 10,
-    partition reading) on the plain path: time per solve (one warmup, one timed), history
-    MACs/s and algorithmic GB/s, the rel-L2 difference from the full-memory result (the
-    paper's error of a memory mode) and, with the oracle, the largest sine-mode error against
-    the oracle's recursion for that mode."""
+    """The same workload under short memory (L = 1000 steps; plain and blocked paths) and
+    adaptive memory (a = 2, 4, 10, partition reading; plain path): time per solve (one warmup,
+    one timed), history MACs/s and, on the plain path, algorithmic GB/s, the rel-L2
+    difference from the full-memory result (the paper's error of a memory mode) and, with the
+    oracle, the largest sine-mode error against the oracle's recursion for that mode."""
     import torch
     from paper_1004_5128_amd import gl, workloads as W
     p, n = w["problem"], w["nsteps"]
     P = W.npoints(p)
     u0 = torch.as_tensor(w["u0"], dtype=torch.float64).cuda()
     out = {}
-    for name, spec in MODE_RUNS:
+    for name, path, spec in MODE_RUNS:
         mem = W.memory(spec["mode"], **{k: v for k, v in spec.items() if k != "mode"})
         log("memory mode", name)
-        with gl.Solver(p, mem, u0, max_steps=n) as s:
+        with gl.Solver(p, mem, u0, max_steps=n, sum_path=path) as s:
             terms = sum(s.schedule_terms(k) for k in range(n))
             s.advance(n)
             torch.cuda.synchronize()
@@ -322,10 +325,11 @@ def run_memory_modes(w, u_full, oracle_modes):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             uT = s.state().cpu().numpy()
-        d = {"ms_per_solve": dt * 1e3, "history_macs_per_solve": P * terms,
+        d = {"path": path, "ms_per_solve": dt * 1e3, "history_macs_per_solve": P * terms,
              "history_macs_per_s": P * terms / dt,
-             "algorithmic_gbs": 4 * P * (terms - n) / dt / 1e9,
              "rel_l2_vs_full_memory": float(np.linalg.norm(uT - u_full) / np.linalg.norm(u_full))}
+        if path == "gemv":
+            d["algorithmic_gbs"] = 4 * P * (terms - n) / dt / 1e9
         if oracle_modes is not None:
             import oracle
             c0 = modal(w["u0"], p, MODES)

@@ -82,10 +82,12 @@ typedef int32_t gl_status;
 /* How the history sum is evaluated. */
 #define GL_SUM_GEMV_FP32 0       /* every step reads its history rows once, FP32 loads,
                                     FP64 accumulation */
-#define GL_SUM_TOEPLITZ_BF16X3 1 /* full memory only: blocks of B steps take the part of their
-                                    sums over rows before the block as one Toeplitz-weight x
-                                    history product on BF16 matrix cores (hi + lo split, three
-                                    products, FP32 accumulation); the rest in FP64 */
+#define GL_SUM_TOEPLITZ_BF16X3 1 /* full or short memory: blocks of B steps take the part of
+                                    their sums over rows before the block as one Toeplitz-weight
+                                    x history product on BF16 matrix cores (hi + lo split, three
+                                    products, FP32 accumulation; with short memory the weights
+                                    past the window are zero and only the rows within reach are
+                                    read); the rest in FP64. Adaptive memory: GL_EUNSUPPORTED */
 
 typedef struct gl_problem {
     int32_t ndim;     /* 1 or 2 */

@@ -129,9 +129,9 @@ gl_status validate(const gl_problem *probs, int32_t nprob, const gl_options *opt
     if (opt->block_B != 0 && opt->block_B != 32 && opt->block_B != 64 && opt->block_B != 128 &&
         opt->block_B != 256 && opt->block_B != 512)
         return fail(nullptr, GL_EINVAL, "gl_init: block_B must be 0, 32, 64, 128, 256 or 512");
-    if (opt->sum_path == GL_SUM_TOEPLITZ_BF16X3 && opt->mem_mode != GL_MEM_FULL)
+    if (opt->sum_path == GL_SUM_TOEPLITZ_BF16X3 && opt->mem_mode == GL_MEM_ADAPTIVE)
         return fail(nullptr, GL_EUNSUPPORTED,
-                    "gl_init: the Toeplitz path sums full memory only (mem_mode must be FULL)");
+                    "gl_init: the Toeplitz path sums full or short memory (not adaptive)");
     for (int32_t i = 0; i < nprob; ++i) {
         const gl_problem &p = probs[i];
         if (p.ndim != 1 && p.ndim != 2)
@@ -292,7 +292,18 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
             if ((st = dev_alloc(ctx, &pb.psi_tab, 16 * (size_t)tab_len))) return st;
             if ((st = dev_alloc(ctx, &pb.old, (size_t)ctx->B * pb.P))) return st;
             if (ctx->B2 && (st = dev_alloc(ctx, &pb.old2, (size_t)ctx->B2 * pb.P))) return st;
-            gl::launch_psi_tables(pb.psi, npsi, tab_len, pb.psi_tab, ctx->stream);
+            // short memory (eq. (22)) is full memory with psi(m) = 0 for m > L
+            const int64_t nkeep = opt.mem_mode == GL_MEM_SHORT ? std::min(npsi, opt.short_L + 1) : npsi;
+            pb.psi_blk = pb.psi;
+            if (nkeep < npsi) {
+                if ((st = dev_alloc(ctx, &pb.psi_blk, npsi))) return st;
+                HIP_TRY(ctx, hipMemcpyAsync(pb.psi_blk, pb.psi, nkeep * sizeof(double),
+                                            hipMemcpyDeviceToDevice, ctx->stream));
+                // zeros past the window: a chunk reduction over no chunks writes 0.0
+                gl::launch_old_reduce(nullptr, 0, 1, npsi - nkeep, pb.psi_blk + nkeep, nullptr,
+                                      ctx->stream);
+            }
+            gl::launch_psi_tables(pb.psi_blk, nkeep, tab_len, pb.psi_tab, ctx->stream);
             HIP_TRY(ctx, hipGetLastError());
         }
     }
@@ -444,6 +455,10 @@ gl_status step_gemv(gl_ctx *ctx) {
 gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int BM,
                      int64_t k_out, int64_t j_lo, int64_t j_hi, double *out, const double *base,
                      int gemm_id, int reduce_id) {
+    if (j_hi <= j_lo)  // no rows in the window: the sums are the base (or zero)
+        return timed(ctx, reduce_id, [&] {
+            gl::launch_old_reduce(ctx->tpart, 0, BM, pb.P, out, base, ctx->stream);
+        });
     const int64_t kchunk = chunk_rows(ctx, BM, pb.P, j_hi - j_lo);
     const int nchunk = gl::toeplitz_chunks(j_hi - j_lo, kchunk);
     if (nchunk > 1 && (int64_t)nchunk * BM * pb.P > ctx->tpart_len)
@@ -459,11 +474,19 @@ gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld
     });
 }
 
+// First history row that can reach step k_out or later: with short memory of L steps the
+// weights of rows before k_out - L are zero (rounded down to the product kernel's 32-row
+// alignment), otherwise row 0.
+int64_t window_lo(const gl_ctx *ctx, int64_t k_out) {
+    if (ctx->opt.mem_mode != GL_MEM_SHORT) return 0;
+    return std::max<int64_t>(0, (k_out - ctx->opt.short_L) / 32 * 32);
+}
+
 // old[b] = sum_{j < k0} psi(k0 + b - j) hist[j] for b < B.
 gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int64_t k0,
                     double *old) {
-    return block_sums(ctx, pb, hist, ld, ctx->B, k0, 0, k0, old, nullptr, GL_KERNEL_TOEPLITZ,
-                      GL_KERNEL_OLD_REDUCE);
+    return block_sums(ctx, pb, hist, ld, ctx->B, k0, window_lo(ctx, k0), k0, old, nullptr,
+                      GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE);
 }
 
 // Steps of the blocked path that one launch can take from step k: at most the fusion
@@ -495,14 +518,15 @@ gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
     }
     if (k1 > k0 && pb.old2_k1 != k1) {
         // Old2 holds Old (rows of the sub-block's steps) + the product over rows k0 .. k1-1
-        if ((st = block_sums(ctx, pb, pb.H, pb.ld, ctx->B2, k1, k0, k1, pb.old2,
+        if ((st = block_sums(ctx, pb, pb.H, pb.ld, ctx->B2, k1,
+                             std::max(k0, window_lo(ctx, k1)), k1, pb.old2,
                              k0 > 0 ? pb.old + (k1 - k0) * pb.P : nullptr, GL_KERNEL_SUBBLOCK,
                              GL_KERNEL_SUB_REDUCE)) != GL_OK)
             return st;
         pb.old2_k1 = k1;
     }
     gl::BlockStepArgs args{};
-    args.psi = pb.psi;
+    args.psi = pb.psi_blk;
     args.H = pb.H;
     args.ld = pb.ld;
     args.P = pb.P;
@@ -843,7 +867,7 @@ gl_status gl_history_sum(gl_ctx *ctx, int32_t iprob, int64_t k, const float *his
             if (st != GL_OK) return st;
             base = pbm.old + b * pbm.P;
         }
-        t_end = b + 1;
+        t_end = std::min(b + 1, t_end);  // the schedule's terms m <= b (short memory: <= L)
     }
     const int nsplit = gl::gemv_splits(t_end, pb.P, ctx->tune.gemv_groups);
     gl::launch_hist_gemv(hist, ld, pb.P, pb.psi, ctx->d_runs + rb, nruns, k, 0, t_end, nsplit,

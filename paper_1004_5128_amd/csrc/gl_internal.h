@@ -62,6 +62,8 @@ struct Problem {
     int64_t offset = 0;   // first point of this problem in concatenated arrays
     double *psi = nullptr;   // [max_steps + 1] FP64 weights
     double *dpsi = nullptr;  // [max_steps + 1] d psi / d gamma
+    double *psi_blk = nullptr;  // weights of the blocked path: psi, zero past a short-memory
+                                // window (the same array as psi otherwise)
     float *H = nullptr;      // [(max_steps + 1) * ld] FP32 history, row j = delta[j] (eq. 17)
     double *u[2] = {nullptr, nullptr};  // FP64 state, double-buffered
     int cur = 0;             // u[cur] holds the current step

@@ -27,12 +27,12 @@ def gpu_adjoint(p, mem, u0, n, target, sum_path="gemv", ckpt_every=0, block_B=0)
 
 CASES = [("linear", W.memory("full"), "gemv"), ("fisher", W.memory("full"), "gemv"),
          ("linear", W.memory("short", L=9), "gemv"), ("fisher", W.memory("full"), "toeplitz"),
-         ("none", W.memory("full"), "toeplitz")]
+         ("none", W.memory("full"), "toeplitz"), ("linear", W.memory("short", L=70), "toeplitz")]
 
 
 @pytest.mark.parametrize("rxn,mem,path", CASES,
                          ids=["lin-full-gemv", "fisher-full-gemv", "lin-short-gemv",
-                              "fisher-full-toeplitz", "none-full-toeplitz"])
+                              "fisher-full-toeplitz", "none-full-toeplitz", "lin-short-toeplitz"])
 def test_adjoint_matches_oracle(rxn, mem, path):
     p = W.problem(2, 14, 0.7, 1.0, 0.05, rxn=rxn, rate=0.3)
     n = 300

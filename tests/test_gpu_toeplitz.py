@@ -159,12 +159,67 @@ def test_fused_steps_do_not_depend_on_grouping(dims, B, sub):
     assert rel_l2(outs[0], oracle.run(p, W.memory("full"), u0, n)) <= TOL_MFMA
 
 
-def test_toeplitz_needs_full_memory():
+def test_toeplitz_rejects_adaptive_memory():
     G = gl()
     p = W.problem(2, 8, 0.7, 1.0, 0.1)
     with pytest.raises(G.GLError) as e:
         G.Solver(p, W.memory("adaptive", a=2), np.zeros(64), max_steps=10, sum_path="toeplitz")
     assert e.value.status == G.GL_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("L,B", [(0, 256), (9, 256), (40, 64), (300, 256), (1000, 256),
+                                 (300, 32), (700, 512)])
+def test_short_memory_blocked_matches_oracle(L, B):
+    # short memory (eq. (22)) on the blocked path: the weights past the window are zero in
+    # the product tables and the in-block sums, and each product reads only the rows that can
+    # reach its steps
+    w = W.cfg2(n=48, nsteps=1100)
+    mem = W.memory("short", L=L)
+    print_case("short blocked", L, B)
+    got = gpu_run(w["problem"], mem, w["u0"], w["nsteps"], sum_path="toeplitz", block_B=B)
+    ref = oracle.run(w["problem"], mem, w["u0"], w["nsteps"])
+    assert rel_l2(got, ref) <= TOL_MFMA, rel_l2(got, ref)
+
+
+def test_short_memory_longer_than_run_equals_full_blocked():
+    w = W.cfg2(n=40, nsteps=600)
+    print_case("short L >= n blocked")
+    full = gpu_run(w["problem"], W.memory("full"), w["u0"], 600, sum_path="toeplitz", block_B=64)
+    short = gpu_run(w["problem"], W.memory("short", L=600), w["u0"], 600, sum_path="toeplitz",
+                    block_B=64)
+    assert np.array_equal(full, short)
+
+
+@pytest.mark.parametrize("L", [100, 1500])
+def test_short_memory_block_history_sum_matches_oracle(L):
+    gamma, kmax, P = 0.6, 3000, 1000
+    print_case("toeplitz short history_sum", L)
+    rng = np.random.default_rng(77)
+    H = rng.uniform(-1.0, 1.0, (kmax + 1, P)).astype(np.float32)
+    Hd = torch.as_tensor(H).cuda()
+    p = W.problem(1, P, gamma, 1.0, 0.05)
+    mem = W.memory("short", L=L)
+    psi = oracle.psi(gamma, kmax)
+    with gl().Solver(p, mem, np.zeros(P), max_steps=kmax, sum_path="toeplitz", block_B=64) as s:
+        for k in (5, 64, 130, 1000, 2049, kmax):
+            got = s.history_sum(k, Hd).cpu().numpy()
+            ref = oracle.history_sum(gamma, mem, k, H)
+            scale = np.sum(np.abs(psi[:min(L, k) + 1]))
+            assert np.abs(got - ref).max() <= TOL_MFMA * scale, (k, np.abs(got - ref).max())
+
+
+def test_cfg2_full_size_short_memory_blocked_modal_parity():
+    w = W.cfg2()
+    p = w["problem"]
+    mem = W.memory("short", L=1000)
+    print_case(w["name"], "short 1000 blocked")
+    got = gpu_run(p, mem, w["u0"], w["nsteps"], sum_path="toeplitz")
+    modes = [(1, 1), (1, 3), (3, 1), (3, 3), (2, 2), (1, 5), (5, 5)]
+    c0 = _modal(w["u0"], p, modes)
+    ref = np.array([c0[i] * oracle.mode_run(p, mem, a, b, 1.0, w["nsteps"])[-1]
+                    for i, (a, b) in enumerate(modes)])
+    cg = _modal(got, p, modes)
+    assert np.abs(cg - ref).max() <= TOL_MFMA * np.abs(ref).max()
 
 
 def _modal(u, p, modes):
