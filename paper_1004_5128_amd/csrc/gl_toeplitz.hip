@@ -223,6 +223,18 @@ __global__ __launch_bounds__(gemm_threads<BM>(), BM >= 512 ? 1 : 2) void toeplit
         }
     };
 
+    // The A operand of output row b at K step jt, 16-row step q, lane half g is the 16-byte word
+    // of table index idx = k0 + b - jt - 16q - 8g - 7 + kPsiPad: hi copy s = idx mod 8, word
+    // (idx - s)/8 - psi_w0(jt) of the staged slice.  With k0, jt (and so every K step start)
+    // multiples of 32, s = (b + 1) mod 8 and the word is (b + 1)/8 + kTK/8 - 2q - g, the same
+    // for every K step: one LDS word per lane and row block, less 2q.
+    int a_word[RB];
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+        const int b = (wm * RB + i) * 32 + (lane & 31);
+        a_word[i] = ((b + 1) & 7) * NW + ((b + 1) >> 3) + kTK / 8 - g;
+    }
+
     if (j_begin < j_end) {
         load_tile(j_begin);
         load_psi(j_begin);
@@ -236,18 +248,14 @@ __global__ __launch_bounds__(gemm_threads<BM>(), BM >= 512 ? 1 : 2) void toeplit
 #pragma unroll
         for (int q = 0; q < kTK / 16; ++q) {
             // A operands of this 16-row step for the wave's row blocks: weights of rows
-            // jt+16q+8g+7-p, p = 0..7, i.e. psi(mstart + p), from the staged table slice;
-            // B operands for all its point blocks; then the three products per accumulator
-            const int64_t w0 = psi_w0(jt);
+            // jt+16q+8g+7-p, p = 0..7, i.e. psi(mstart + p), from the staged table slice (word
+            // a_word[i] - 2q, see below); B operands for all its point blocks; then the three
+            // products per accumulator
             bf16x8_t Ah[RB], Al[RB], Bh[CB], Bl[CB];
 #pragma unroll
             for (int i = 0; i < RB; ++i) {
-                const int b = (wm * RB + i) * 32 + (lane & 31);
-                const int64_t idx = k0 + b - jt - 16 * q - 8 * g - 7 + kPsiPad;
-                const int s = (int)(idx & 7);
-                const int w = (int)(((idx - s) >> 3) - w0);
-                Ah[i] = __builtin_bit_cast(bf16x8_t, lpsi[s * NW + w]);
-                Al[i] = __builtin_bit_cast(bf16x8_t, lpsi[(8 + s) * NW + w]);
+                Ah[i] = __builtin_bit_cast(bf16x8_t, lpsi[a_word[i] - 2 * q]);
+                Al[i] = __builtin_bit_cast(bf16x8_t, lpsi[a_word[i] + 8 * NW - 2 * q]);
             }
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
