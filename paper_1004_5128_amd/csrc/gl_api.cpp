@@ -158,6 +158,12 @@ gl_status validate(const gl_problem *probs, int32_t nprob, const gl_options *opt
     return GL_OK;
 }
 
+// In-block launches hand chain carries to the next launch when a sub-block (the block with
+// one level) has at most 32 steps: the rows a carry sums then fit one batch.
+bool carry_ok(const gl_ctx *ctx) {
+    return ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3 && (ctx->B2 ? ctx->B2 : ctx->B) <= 32;
+}
+
 // A tuning variable's value, or nullptr when it is unset or empty.
 const char *env_value(const char *name) {
     const char *v = std::getenv(name);
@@ -227,7 +233,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
                 2 * (size_t)pb.P * sizeof(double);
         if (toep)
             need += 16 * (size_t)tab_len * sizeof(uint16_t) +
-                    (size_t)(ctx->B + ctx->tune.sub_B) * pb.P * sizeof(double);
+                    (size_t)(ctx->B + ctx->tune.sub_B + 2 * gl::kMaxFuse) * pb.P * sizeof(double);
     }
     ctx->C = opt.ckpt_every > 0 ? opt.ckpt_every : 500;
     const int64_t nsnap = opt.max_steps / ctx->C + 1;
@@ -292,6 +298,9 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
             if ((st = dev_alloc(ctx, &pb.psi_tab, 16 * (size_t)tab_len))) return st;
             if ((st = dev_alloc(ctx, &pb.old, (size_t)ctx->B * pb.P))) return st;
             if (ctx->B2 && (st = dev_alloc(ctx, &pb.old2, (size_t)ctx->B2 * pb.P))) return st;
+            if (carry_ok(ctx))
+                for (int c = 0; c < 2; ++c)
+                    if ((st = dev_alloc(ctx, &pb.carry[c], (size_t)gl::kMaxFuse * pb.P))) return st;
             // short memory (eq. (22)) is full memory with psi(m) = 0 for m > L
             const int64_t nkeep = opt.mem_mode == GL_MEM_SHORT ? std::min(npsi, opt.short_L + 1) : npsi;
             pb.psi_blk = pb.psi;
@@ -401,6 +410,7 @@ gl_status load_initial(gl_ctx *ctx, const double *u0) {
         pb.cur = 0;
         pb.old_k0 = -1;
         pb.old2_k1 = -1;
+        pb.carry_k = -1;
         HIP_TRY(ctx, hipMemcpyAsync(pb.u[0], u0 + pb.offset, pb.P * sizeof(double),
                                     hipMemcpyDeviceToDevice, ctx->stream));
         HIP_TRY(ctx, hipMemcpyAsync(pb.snap, u0 + pb.offset, pb.P * sizeof(double),
@@ -558,7 +568,29 @@ gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
     args.b2 = (int32_t)b2;
     args.s = (int32_t)s;
     args.write_history = write_history;
-    return timed(ctx, GL_KERNEL_TRIANGLE, [&] { gl::launch_block_step(args, ctx->stream); });
+    // chain carries between consecutive launches of a sub-block
+    const int64_t sub_len = ctx->B2 ? ctx->B2 : ctx->B;
+    int out_buf = 0;
+    if (carry_ok(ctx)) {
+        if (pb.carry_k == k && s <= pb.carry_n) {
+            args.carry_in = pb.carry[pb.carry_cur];
+            out_buf = pb.carry_cur ^ 1;
+        }
+        if (b2 + s < sub_len) {
+            args.carry_out = pb.carry[out_buf];
+            args.n_next = (int32_t)std::min<int64_t>(ctx->tune.fuse, sub_len - (b2 + s));
+        }
+    }
+    st = timed(ctx, GL_KERNEL_TRIANGLE, [&] { gl::launch_block_step(args, ctx->stream); });
+    if (st != GL_OK) return st;
+    if (args.carry_out) {
+        pb.carry_k = k + s;
+        pb.carry_n = args.n_next;
+        pb.carry_cur = out_buf;
+    } else {
+        pb.carry_k = -1;
+    }
+    return GL_OK;
 }
 
 // Up to `limit` steps on the blocked path (one launch per problem; *done receives the
@@ -793,7 +825,10 @@ gl_status gl_adjoint(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *
                     "gl_adjoint: the adaptive schedule's transpose is not built (full or short "
                     "memory only)");
     gl_status st = adjoint_impl(ctx, dL_duT, dL_du0, dparams);
-    for (gl::Problem &pb : ctx->probs) pb.old_k0 = pb.old2_k1 = -1;  // sums reused as scratch
+    for (gl::Problem &pb : ctx->probs) {  // sums and carries reused by the recomputation
+        pb.old_k0 = pb.old2_k1 = -1;
+        pb.carry_k = -1;
+    }
     if (st != GL_OK) return st;
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return resolve_profile(ctx);
@@ -863,6 +898,7 @@ gl_status gl_history_sum(gl_ctx *ctx, int32_t iprob, int64_t k, const float *his
         const int64_t b = k % ctx->B, k0 = k - b;
         if (k0 > 0) {
             pbm.old_k0 = pbm.old2_k1 = -1;  // old[] is reused as scratch here
+            pbm.carry_k = -1;
             gl_status st = block_old(ctx, pbm, hist, ld, k0, pbm.old);
             if (st != GL_OK) return st;
             base = pbm.old + b * pbm.P;

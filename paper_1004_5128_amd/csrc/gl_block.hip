@@ -20,6 +20,15 @@
 // arithmetic in the same order, so all copies of a value are bit-identical, and because the
 // chain above does not depend on where a launch starts, any grouping of the steps into
 // launches gives the same bits (the adjoint's recomputation relies on this).
+//
+// Carry: in a sub-block of at most 32 steps a launch also continues, for the points of its
+// own tile, the chains of the next launch's steps over every row before that launch
+// (Old + Old2, rows k1 .. k-1 from the history, then its own rows k .. k+s-1) and writes them
+// out.  The next launch starts its chains there for its whole region (tile and halo, written
+// by the neighbouring tiles) instead of re-reading and re-summing the sub-block's rows at
+// every halo point; the values are the same chain in the same order, so the bits do not
+// change.  A launch without a carry (a sub-block's first, or the first after a restart) sums
+// the rows itself.
 #include <hip/hip_runtime.h>
 
 #include "gl_internal.h"
@@ -29,8 +38,9 @@ namespace gl {
 constexpr int kStepThreads = 1024;
 constexpr int kTile2 = 16;   // 2D tile side
 constexpr int kTile1 = 256;  // 1D tile length
-constexpr int kRowBatch = 32; // history rows loaded together
+constexpr int kRowBatch = 32; // history rows loaded together (and the most a carry sums)
 constexpr int kWin = 16;      // rows per weight window
+constexpr int kTilePts = 256; // points of a tile
 
 template <int S>
 struct StepGeom {
@@ -62,6 +72,8 @@ template <int S>
 __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs a) {
     using G = StepGeom<S>;
     __shared__ double lu[2][G::kULen];
+    __shared__ float lrows[kRowBatch][kTilePts];  // carry: the tile's rows k1 .. k+s-1
+    __shared__ double lpsi[kRowBatch + 2 * kMaxFuse];  // carry: psi(0 ..)
     const int tid = threadIdx.x;
     const bool two = a.ndim == 2;
     const int tx = two ? kTile2 : kTile1, ty = two ? kTile2 : 1, hy = two ? 1 : 0;
@@ -74,6 +86,8 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
     const int64_t gy0 = two ? (int64_t)(tile / ntx) * ty - S : 0;
     const int s = a.s;
     const int64_t k = a.k;
+    const bool from_carry = a.carry_in != nullptr;
+    const bool to_carry = a.carry_out != nullptr;  // the host keeps b2 + s <= kRowBatch then
 
     // u[k] on the u region (zero outside the grid), held in registers until the history
     // loads below are in flight too
@@ -92,6 +106,7 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
     int ux[G::kPts];       // index in the u region
     int lvl[G::kPts];      // evaluated at steps i <= lvl (distance to the step-0 region's
                            // edge); -1: no grid point in this slot
+    int tl[G::kPts];       // index in the tile (points with lvl >= S - 1)
     int64_t q[G::kPts];    // grid index
 #pragma unroll
     for (int n = 0; n < G::kPts; ++n) {
@@ -103,8 +118,16 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
         if (two) l = min(l, min(ry, h0 - 1 - ry));
         lvl[n] = ok ? l : -1;
         ux[n] = (ry + hy) * uw + rx + 1;
+        tl[n] = (rx - (S - 1)) + (ry - (S - 1) * hy) * tx;
         q[n] = ok ? gy * nx + gx : 0;
     }
+    // carry work: lane t continues, for tile point pt = t mod 256 (x fastest), the chains of
+    // the next launch's steps 2 cp and 2 cp + 1, cp = t / 256 (uniform per wave)
+    static_assert(kStepThreads == 4 * kTilePts && kMaxFuse == 8, "four step pairs per point");
+    const int pt = tid % kTilePts, cp = tid / kTilePts;
+    const int64_t cgx = gx0 + S + pt % tx, cgy = gy0 + S * hy + pt / tx;
+    const bool cok = to_carry && cgx < nx && cgy < ny;
+    const int64_t cq = cok ? cgy * nx + cgx : 0;
 
     // Chains of the s steps up to row k - 1: Old + Old2, then the sub-block's rows.  All loads
     // are issued before any is used and are unconditional: slots without a grid point read
@@ -116,16 +139,33 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
         qb8[n] = (uint32_t)q[n] * 8u;
         qb4[n] = (uint32_t)q[n] * 4u;
     }
+    // the chains' start: the previous launch's carry, or Old + Old2
     double pv[G::kPts][S];
+    const double *cstart = from_carry ? a.carry_in : a.pre;
+    const int crow = from_carry ? 0 : a.pre_row;
 #pragma unroll
     for (int i = 0; i < S; ++i) {
-        const char *o = reinterpret_cast<const char *>(a.pre + (int64_t)(a.pre_row + min(i, s - 1)) * P);
+        const char *o = reinterpret_cast<const char *>(cstart + (int64_t)(crow + min(i, s - 1)) * P);
 #pragma unroll
         for (int n = 0; n < G::kPts; ++n) pv[n][i] = *reinterpret_cast<const double *>(o + qb8[n]);
     }
     const int nr = a.b2;  // rows k - nr .. k - 1
     const float *rows = a.H + (k - nr) * a.ld;
     float v[G::kPts][kRowBatch];
+    // carry: Old + Old2 of the lane's two next steps, and (starting from a carry, when no slot
+    // loads rows) rows cp, cp + 4, ... of k - nr .. k - 1 at its tile point, into slot 0's row
+    // registers
+    double pn[2];
+    if (to_carry) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            pn[h] = a.pre[(int64_t)(a.pre_row + s + min(2 * cp + h, a.n_next - 1)) * P + cq];
+        if (from_carry) {
+#pragma unroll
+            for (int e = 0; e < kRowBatch / 4; ++e)
+                if (4 * e < nr) v[0][e] = rows[(int64_t)min(4 * e + cp, nr - 1) * a.ld + cq];
+        }
+    }
     auto load_rows = [&](int j) {
         // groups of 8 rows holding at least one row of the batch (uniform branches, so the
         // loads still issue together)
@@ -144,16 +184,20 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
             }
         }
     };
-    load_rows(0);
+    if (!from_carry) load_rows(0);
     double acc[G::kPts][S];
 #pragma unroll
     for (int n = 0; n < G::kPts; ++n)
 #pragma unroll
         for (int i = 0; i < S; ++i) {
-            acc[n][i] = 0.0;
-            acc[n][i] += a.has_pre ? pv[n][i] : 0.0;
+            if (from_carry) {
+                acc[n][i] = pv[n][i];
+            } else {
+                acc[n][i] = 0.0;
+                acc[n][i] += a.has_pre ? pv[n][i] : 0.0;
+            }
         }
-    for (int j = 0; j < nr; j += kRowBatch) {
+    for (int j = 0; j < (from_carry ? 0 : nr); j += kRowBatch) {
         if (j > 0) load_rows(j);
 #pragma unroll
         for (int h = 0; h < kRowBatch / kWin; ++h) {
@@ -193,6 +237,23 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
             lu[1][idx] = 0.0;
         }
     }
+    if (to_carry && tid < kRowBatch + 2 * kMaxFuse) lpsi[tid] = a.psi[tid];
+
+    if (to_carry) {  // the tile's rows k - nr .. k - 1 for the carry
+        if (from_carry) {
+#pragma unroll
+            for (int e = 0; e < kRowBatch / 4; ++e)
+                if (4 * e + cp < nr) lrows[4 * e + cp][pt] = v[0][e];
+        } else {
+#pragma unroll
+            for (int n = 0; n < G::kPts; ++n)
+                if (lvl[n] >= S - 1) {
+#pragma unroll
+                    for (int t = 0; t < kRowBatch; ++t)
+                        if (t < nr) lrows[t][tl[n]] = v[n][t];
+                }
+        }
+    }
 
     float dl[G::kPts][S];  // the lane's delta rows k .. k + i - 1, FP32 as stored
 #pragma unroll
@@ -218,6 +279,7 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
             const double unew = u + a.dt * step_reaction(a.rxn, a.rate, u) + a.r * Sv;
             un[x] = unew;
             if (lvl[n] >= S - 1) {  // a point of the tile: results go out
+                if (to_carry) lrows[nr + i][tl[n]] = df;  // nr + i < nr + s <= kRowBatch
                 if (a.write_history) a.H[kk * a.ld + q[n]] = df;
                 if (a.S_out) a.S_out[(int64_t)i * P + q[n]] = Sv;
                 if (i == s - 1) a.u_next[q[n]] = unew;
@@ -226,6 +288,35 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
                     a.snap[(a.snap_row0 + __builtin_popcount(a.snap_mask & ((1u << i) - 1u))) * P +
                            q[n]] = unew;
             }
+        }
+    }
+
+    // The next launch's chains over rows k1 .. k+s-1 for this tile's points: Old + Old2, then
+    // rows k - nr .. k+s-1 in ascending order (LDS row jj = history row k - nr + jj), row jj
+    // being m = nr + s - jj + i steps back from the next launch's step i.
+    if (to_carry) {
+        __syncthreads();
+        if (cok) {
+            const int m0 = nr + s, i0 = 2 * cp;
+            double c[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                c[h] = 0.0;
+                c[h] += a.has_pre ? pn[h] : 0.0;
+            }
+            // the pair of weights slides down one entry per row
+            double w1 = lpsi[m0 + i0 + 1], w0 = lpsi[m0 + i0];
+#pragma unroll 8
+            for (int jj = 0; jj < m0; ++jj) {
+                const double dv = (double)lrows[jj][pt];
+                c[0] = fma(w0, dv, c[0]);
+                c[1] = fma(w1, dv, c[1]);
+                w1 = w0;
+                w0 = lpsi[max(m0 + i0 - jj - 1, 0)];
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (i0 + h < a.n_next) a.carry_out[(int64_t)(i0 + h) * P + cq] = c[h];
         }
     }
 }

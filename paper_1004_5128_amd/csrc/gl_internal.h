@@ -64,6 +64,10 @@ struct Problem {
     double *dpsi = nullptr;  // [max_steps + 1] d psi / d gamma
     double *psi_blk = nullptr;  // weights of the blocked path: psi, zero past a short-memory
                                 // window (the same array as psi otherwise)
+    double *carry[2] = {nullptr, nullptr};  // in-block chain carries, kMaxFuse x P each
+    int64_t carry_k = -1;   // step the valid carry starts at (-1: none)
+    int32_t carry_n = 0;    // steps it covers
+    int32_t carry_cur = 0;  // buffer holding it
     float *H = nullptr;      // [(max_steps + 1) * ld] FP32 history, row j = delta[j] (eq. 17)
     double *u[2] = {nullptr, nullptr};  // FP64 state, double-buffered
     int cur = 0;             // u[cur] holds the current step
@@ -189,6 +193,13 @@ struct BlockStepArgs {
                             // are summed point by point)
     int32_t s;              // steps in this launch (1 .. kMaxFuse), inside one sub-block
     int32_t write_history;  // 0: leave history rows k .. k + s - 1 untouched (recomputation)
+    // Carry (sub-blocks of at most 32 steps): carry_in, nullable, holds for every point the
+    // chains of this launch's steps (row i: step k + i) over all rows before k, as the
+    // previous launch left them; carry_out, nullable, receives those of the next launch's
+    // n_next steps over all rows before k + s, for this launch's tile points.
+    const double *carry_in;
+    double *carry_out;
+    int32_t n_next;
 };
 
 constexpr int kMaxFuse = 8;
