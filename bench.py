@@ -377,6 +377,48 @@ def probe_product(k, reps=3):
     print(json.dumps({"probe": "toeplitz product", "k": k, "points": P, "ms": out}), flush=True)
 
 
+def paper_fig3(reps=2):
+    """The short- vs adaptive-memory comparison of Sec. 3.2 (the experiment of its Fig. 3) on
+    the GPU's plain path: for each of four gamma values, full memory and short (L) and
+    adaptive (a) memory sweeps, each with its history terms, GPU time per run (best of
+    `reps`, after one warmup) and its error relative to full memory.  At 400 points a run is
+    bound by its 3000 launches, so the term count is the cost to read the trade-off by."""
+    import torch
+    from paper_1004_5128_amd import gl, workloads as W
+    out = {}
+    for gamma in (0.5, 0.75, 0.9, 0.95):
+        w = W.paper_fig3(gamma)
+        p, n = w["problem"], w["nsteps"]
+        u0 = torch.as_tensor(w["u0"], dtype=torch.float64).cuda()
+        rows, full = [], None
+        mems = ([("full", 0, W.memory("full"))] +
+                [("short", L, W.memory("short", L=L)) for L in (10, 25, 50, 100, 200, 400, 800)] +
+                [("adaptive", a, W.memory("adaptive", a=a)) for a in (2, 3, 4, 6, 10, 20)])
+        for mode, par, mem in mems:
+            with gl.Solver(p, mem, u0, max_steps=n) as s:
+                terms = sum(s.schedule_terms(k) for k in range(n))
+                s.advance(n)
+                best = None
+                for _ in range(reps):
+                    s.reset(u0)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    s.advance(n)
+                    torch.cuda.synchronize()
+                    dt = time.perf_counter() - t0
+                    best = dt if best is None else min(best, dt)
+                uT = s.state().cpu().numpy()
+            if full is None:
+                full = uT
+            rows.append({"mode": mode, "param": par, "history_terms": terms,
+                         "gpu_ms": best * 1e3,
+                         "error_vs_full_pct": 100 * float(np.linalg.norm(uT - full) /
+                                                          np.linalg.norm(full))})
+        out["gamma_%g" % gamma] = rows
+    print(json.dumps({"probe": "paper fig3 (short vs adaptive memory)", "results": out}),
+          flush=True)
+
+
 def probe_hipblaslt(reps=10):
     """Vendor BF16 GEMMs (torch.matmul -> hipBLASLt) on the same GPU for comparison: square
     4096..16384 and the block product's shape (256 x 19968) x (19968 x 65536)."""
@@ -422,7 +464,14 @@ def main():
                     help="time the block product alone at step K (for counter collection)")
     ap.add_argument("--probe-hipblaslt", action="store_true",
                     help="time vendor BF16 GEMMs (torch.matmul) for comparison")
+    ap.add_argument("--paper-fig3", action="store_true",
+                    help="the paper's short vs adaptive memory comparison (Sec. 3.2)")
     args = ap.parse_args()
+    if args.paper_fig3:
+        import torch
+        torch.cuda.set_device(0)
+        paper_fig3()
+        return
     if args.probe_product or args.probe_hipblaslt:
         import torch
         torch.cuda.set_device(0)

@@ -209,3 +209,31 @@ def test_cfg3_full_capacity_prefix_matches_oracle():
     got = gpu_run(w["problem"], w["memory"], w["u0"], n, max_steps=w["nsteps"])
     ref = oracle.run(w["problem"], w["memory"], w["u0"], n)
     assert rel_l2(got, ref) <= TOL_PLAIN
+
+
+@pytest.mark.parametrize("gamma", [0.5, 0.75, 0.9, 0.95])
+def test_paper_fig3_setup_matches_oracle(gamma):
+    # the short- vs adaptive-memory experiment of Sec. 3.2 (20 x 20, point source, 1500
+    # steps): every memory mode on the plain path, full and short memory on the blocked path
+    w = W.paper_fig3(gamma)
+    p, u0, n = w["problem"], w["u0"], w["nsteps"]
+    runs = [(W.memory("full"), "gemv"), (W.memory("full"), "toeplitz"),
+            (W.memory("short", L=100), "gemv"), (W.memory("short", L=800), "toeplitz"),
+            (W.memory("adaptive", a=2), "gemv"), (W.memory("adaptive", a=10), "gemv")]
+    for mem, path in runs:
+        print_case(w["name"], mem["mode"], mem["L"], mem["a"], path)
+        got = gpu_run(p, mem, u0, n, sum_path=path)
+        tol = TOL_PLAIN if path == "gemv" else 1e-5
+        assert rel_l2(got, oracle.run(p, mem, u0, n)) <= tol, (mem, path)
+
+
+@pytest.mark.parametrize("gamma", [0.5, 0.75, 0.9, 1.0])
+def test_paper_fig1_setup_matches_oracle(gamma):
+    # the diffusion examples of Sec. 3.1: 100 x 100, point source, 200 steps, on both paths
+    w = W.paper_fig1(gamma)
+    p, u0, n = w["problem"], w["u0"], w["nsteps"]
+    ref = oracle.run(p, w["memory"], u0, n)
+    print_case(w["name"], "gemv")
+    assert rel_l2(gpu_run(p, w["memory"], u0, n), ref) <= TOL_PLAIN
+    print_case(w["name"], "toeplitz B=64")
+    assert rel_l2(gpu_run(p, w["memory"], u0, n, sum_path="toeplitz", block_B=64), ref) <= 1e-5
