@@ -10,7 +10,8 @@ where every computation lives and where each function cites the passage of
 the paper it follows.  Problems and memory settings are plain dicts, the
 form the seeded workload generators emit:
 
-  problem = {"ndim", "nx", "ny", "dx", "dt", "gamma", "alpha", "rxn", "rate"}
+  problem = {"ndim", "nx", "ny", "nz", "dx", "dt", "gamma", "alpha", "rxn", "rate"}
+            ("ny" and "nz" may be left out below 2D and 3D)
             rxn in {"none", "linear", "fisher"}
   memory  = {"mode", "L", "a", "rule"}
             mode in {"full", "short", "adaptive"},
@@ -30,7 +31,7 @@ RXNS = {"none": 0, "linear": 1, "fisher": 2}
 
 
 class _Problem(C.Structure):
-    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32),
+    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("dx", C.c_double), ("dt", C.c_double), ("gamma", C.c_double),
                 ("alpha", C.c_double), ("rxn", C.c_int32), ("rate", C.c_double)]
 
@@ -64,7 +65,7 @@ def _load():
     lib.orc_run.argtypes = [C.POINTER(_Problem), C.POINTER(_Memory), dp, C.c_int64, dp, C.c_int]
     lib.orc_run.restype = C.c_int
     lib.orc_mode_run.argtypes = [C.POINTER(_Problem), C.POINTER(_Memory), C.c_int32, C.c_int32,
-                                 C.c_double, C.c_int64, dp]
+                                 C.c_int32, C.c_double, C.c_int64, dp]
     lib.orc_mode_run.restype = C.c_int
     lib.orc_history_sum.argtypes = [C.c_double, C.POINTER(_Memory), C.c_int64, fp, C.c_int64,
                                     C.c_int64, dp]
@@ -83,7 +84,8 @@ def _dptr(a):
 
 
 def _problem(p):
-    return _Problem(int(p["ndim"]), int(p["nx"]), int(p.get("ny", 1)), float(p["dx"]),
+    return _Problem(int(p["ndim"]), int(p["nx"]), int(p.get("ny", 1)), int(p.get("nz", 1)),
+                    float(p["dx"]),
                     float(p["dt"]), float(p["gamma"]), float(p["alpha"]),
                     RXNS[p.get("rxn", "none")], float(p.get("rate", 0.0)))
 
@@ -95,7 +97,9 @@ def _memory(m):
 
 
 def npoints(p):
-    return int(p["nx"]) * (int(p.get("ny", 1)) if int(p["ndim"]) == 2 else 1)
+    nd = int(p["ndim"])
+    return (int(p["nx"]) * (int(p.get("ny", 1)) if nd >= 2 else 1) *
+            (int(p.get("nz", 1)) if nd == 3 else 1))
 
 
 def psi(gamma, n):
@@ -145,11 +149,11 @@ def run(problem, memory, u0, nsteps, store_all=False):
     return out.reshape(nsteps + 1, P) if store_all else out
 
 
-def mode_run(problem, memory, p, q, v0, n):
-    """Amplitude v[0..n] of the discrete sine mode (p, q) under the scheme (linear f)."""
+def mode_run(problem, memory, p, q, v0, n, s=1):
+    """Amplitude v[0..n] of the discrete sine mode (p, q[, s]) under the scheme (linear f)."""
     out = np.empty(n + 1, np.float64)
     rc = _load().orc_mode_run(C.byref(_problem(problem)), C.byref(_memory(memory)), int(p),
-                              int(q), float(v0), int(n), _dptr(out))
+                              int(q), int(s), float(v0), int(n), _dptr(out))
     if rc != 0:
         raise ValueError("oracle mode_run: nonlinear reaction or out of memory")
     return out

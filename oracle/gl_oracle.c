@@ -15,14 +15,20 @@
  *
  * Notation (paper, Sec. 2.2): grid u[k][j,l], k = t/dt, stored as
  * u[l*nx + j] with the x1 index j fastest; nx*ny interior points, the
- * points outside held at zero (zero Dirichlet edge, Sec. 3.1).
+ * points outside held at zero (zero Dirichlet edge, Sec. 3.1).  A 3D grid
+ * u[k][j,l,n] is stored as u[(n*ny + l)*nx + j].
  *
  * Readings of the paper taken here (each one is listed with its reason in the
  * design notes of the repository):
  *  - the weights are psi(gamma,m) = (-1)^m binom(1-gamma, m) (eq. 8), built by
  *    the recurrence of eq. (11) from psi(gamma,0) = 1 (eq. 12);
  *  - the stencil delta is the un-normalised 5-point sum of eq. (17) (3-point in
- *    1D, from the x1 row of eq. (15)); dx^2 sits in r = alpha dt^gamma / dx^2;
+ *    1D, from the x1 row of eq. (15); 7-point in 3D, the same sum taken over a
+ *    third axis, for the N-dimensional model of Sec. 1); dx^2 sits in
+ *    r = alpha dt^gamma / dx^2;
+ *  - the weights and the scheme are the same for superdiffusion, 1 < gamma <= 2
+ *    (the recurrence of eq. (11) holds for any gamma); at gamma = 2 every
+ *    weight is 1;
  *  - the reaction term is explicit and outside the GL sum, as in eq. (21):
  *    u[k+1] = u[k] + dt f(u[k]) + r * sum_m psi(gamma,m) delta[k-m];
  *  - short memory (eq. 22) takes the window length L in steps: m = 0..min(L,k);
@@ -47,10 +53,10 @@ enum { ORC_PARTITION = 0, ORC_LITERAL = 1, ORC_UNIT_STRIDE = 2 };
 enum { ORC_RXN_NONE = 0, ORC_RXN_LINEAR = 1, ORC_RXN_FISHER = 2 };
 
 typedef struct {
-    int32_t ndim;      /* 1 or 2 */
-    int32_t nx, ny;    /* interior points per side (ny = 1 in 1D) */
+    int32_t ndim;      /* 1, 2 or 3 */
+    int32_t nx, ny, nz; /* interior points per side (ny = 1 in 1D, nz = 1 below 3D) */
     double dx, dt;     /* grid spacing and time step */
-    double gamma;      /* anomalous exponent, 0 < gamma <= 1 */
+    double gamma;      /* anomalous exponent, 0 < gamma <= 2 */
     double alpha;      /* diffusivity */
     int32_t rxn;       /* ORC_RXN_* */
     double rate;       /* beta (linear decay) or rho (Fisher-KPP) */
@@ -184,22 +190,32 @@ int64_t orc_schedule(const orc_memory *mem, int64_t k, int64_t *ms, double *cs, 
 /* ----------------------------------------------------------- the scheme */
 
 /* delta of eq. (17): u[j+1,l] + u[j-1,l] - 4u[j,l] + u[j,l+1] + u[j,l-1]
- * (1D: u[j+1] - 2u[j] + u[j-1], the x1 row of eq. 15), zero outside the grid. */
+ * (1D: u[j+1] - 2u[j] + u[j-1], the x1 row of eq. 15; 3D: the six neighbours
+ * along three axes minus 6u), zero outside the grid. */
 static void stencil(const orc_problem *pr, const double *u, double *out)
 {
     const int64_t nx = pr->nx, ny = pr->ndim == 1 ? 1 : pr->ny;
-#pragma omp parallel for schedule(static)
-    for (int64_t l = 0; l < ny; ++l) {
-        for (int64_t j = 0; j < nx; ++j) {
-            const int64_t p = l * nx + j;
-            double east = j + 1 < nx ? u[p + 1] : 0.0;
-            double west = j > 0 ? u[p - 1] : 0.0;
-            if (pr->ndim == 1) {
-                out[p] = east - 2.0 * u[p] + west;
-            } else {
-                double north = l + 1 < ny ? u[p + nx] : 0.0;
-                double south = l > 0 ? u[p - nx] : 0.0;
-                out[p] = east + west - 4.0 * u[p] + north + south;
+    const int64_t nz = pr->ndim == 3 ? pr->nz : 1;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t n = 0; n < nz; ++n) {
+        for (int64_t l = 0; l < ny; ++l) {
+            for (int64_t j = 0; j < nx; ++j) {
+                const int64_t p = (n * ny + l) * nx + j;
+                double east = j + 1 < nx ? u[p + 1] : 0.0;
+                double west = j > 0 ? u[p - 1] : 0.0;
+                if (pr->ndim == 1) {
+                    out[p] = east - 2.0 * u[p] + west;
+                } else {
+                    double north = l + 1 < ny ? u[p + nx] : 0.0;
+                    double south = l > 0 ? u[p - nx] : 0.0;
+                    if (pr->ndim == 2) {
+                        out[p] = east + west - 4.0 * u[p] + north + south;
+                    } else {
+                        double up = n + 1 < nz ? u[p + nx * ny] : 0.0;
+                        double down = n > 0 ? u[p - nx * ny] : 0.0;
+                        out[p] = east + west + north + south + up + down - 6.0 * u[p];
+                    }
+                }
             }
         }
     }
@@ -237,7 +253,8 @@ double orc_r(const orc_problem *pr)
 
 static int64_t npoints(const orc_problem *pr)
 {
-    return (int64_t)pr->nx * (pr->ndim == 1 ? 1 : (int64_t)pr->ny);
+    return (int64_t)pr->nx * (pr->ndim == 1 ? 1 : (int64_t)pr->ny) *
+           (pr->ndim == 3 ? (int64_t)pr->nz : 1);
 }
 
 /* Runs nsteps steps of eq. (21) (or its short/adaptive forms, eqs. 22, 24)
@@ -285,16 +302,18 @@ int orc_run(const orc_problem *pr, const orc_memory *mem, const double *u0, int6
 /* The scheme restricted to one discrete sine mode (linear f only).
  * phi[j,l] = sin(p pi (j+1)/(nx+1)) sin(q pi (l+1)/(ny+1)) satisfies
  * delta(phi) = -lam phi with lam = 4 sin^2(p pi / (2(nx+1))) (+ the same in
- * q, ny in 2D), so u[k] = v[k] phi solves eq. (21) exactly when
+ * q, ny in 2D, and in s, nz in 3D), so u[k] = v[k] phi solves eq. (21) exactly
+ * when
  *   v[k+1] = v[k] + dt f(v[k]) - r lam sum_m c psi(gamma,m) v[k-m].
  * Writes v[0..n].  Returns 0, -1 on a nonlinear f or no memory. */
-int orc_mode_run(const orc_problem *pr, const orc_memory *mem, int32_t p, int32_t q, double v0,
-                 int64_t n, double *v)
+int orc_mode_run(const orc_problem *pr, const orc_memory *mem, int32_t p, int32_t q, int32_t s,
+                 double v0, int64_t n, double *v)
 {
     const double pi = 3.14159265358979323846;
     if (pr->rxn == ORC_RXN_FISHER) return -1;
     double lam = 4.0 * pow(sin(p * pi / (2.0 * (pr->nx + 1))), 2);
-    if (pr->ndim == 2) lam += 4.0 * pow(sin(q * pi / (2.0 * (pr->ny + 1))), 2);
+    if (pr->ndim >= 2) lam += 4.0 * pow(sin(q * pi / (2.0 * (pr->ny + 1))), 2);
+    if (pr->ndim == 3) lam += 4.0 * pow(sin(s * pi / (2.0 * (pr->nz + 1))), 2);
     const double r = orc_r(pr);
     double *psi = malloc(sizeof(double) * (size_t)(n + 1));
     int64_t *ms = malloc(sizeof(int64_t) * (size_t)(n + 1));

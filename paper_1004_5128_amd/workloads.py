@@ -7,13 +7,14 @@ FP64 oracle use.  Every random draw comes from ``numpy.random.default_rng``
 seeded with the value stated per workload, drawn in the order written.
 
 Conventions (shared by both sides):
-  * the domain is the unit interval / unit square with N interior points per
-    side and zero values outside (zero Dirichlet edge); dx = 1 / (N + 1) and
-    the interior point j sits at x_j = (j + 1) dx;
-  * a field is stored as u[l * nx + j] (x1 index j fastest);
+  * the domain is the unit interval / square / cube with N interior points
+    per side and zero values outside (zero Dirichlet edge); dx = 1 / (N + 1)
+    and the interior point j sits at x_j = (j + 1) dx;
+  * a field is stored as u[l * nx + j] (x1 index j fastest), in 3D as
+    u[(n * ny + l) * nx + j];
   * dt is chosen from a target r = alpha dt^gamma / dx^2, i.e.
     dt = (r dx^2 / alpha)^(1 / gamma);
-  * problem dict keys: ndim, nx, ny, dx, dt, gamma, alpha, rxn
+  * problem dict keys: ndim, nx, ny, nz, dx, dt, gamma, alpha, rxn
     ("none" | "linear" | "fisher"), rate (f = -rate u or rate u (1 - u));
   * memory dict keys: mode ("full" | "short" | "adaptive"), L (window in
     steps), a (adaptive base), rule ("partition" | "literal" | "unit_stride").
@@ -29,10 +30,11 @@ def dt_for_r(r, dx, alpha, gamma):
 
 
 def problem(ndim, n, gamma, alpha, r, rxn="none", rate=0.0, dt=None, dx=None):
-    """A problem on n interior points per side of the unit interval/square."""
+    """A problem on n interior points per side of the unit interval/square/cube."""
     dx = 1.0 / (n + 1) if dx is None else float(dx)
     dt = dt_for_r(r, dx, alpha, gamma) if dt is None else float(dt)
-    return {"ndim": int(ndim), "nx": int(n), "ny": int(n) if ndim == 2 else 1, "dx": dx,
+    return {"ndim": int(ndim), "nx": int(n), "ny": int(n) if ndim >= 2 else 1,
+            "nz": int(n) if ndim == 3 else 1, "dx": dx,
             "dt": dt, "gamma": float(gamma), "alpha": float(alpha), "rxn": rxn,
             "rate": float(rate)}
 
@@ -42,7 +44,8 @@ def memory(mode="full", L=0, a=2, rule="partition"):
 
 
 def npoints(p):
-    return p["nx"] * (p["ny"] if p["ndim"] == 2 else 1)
+    return (p["nx"] * (p["ny"] if p["ndim"] >= 2 else 1) *
+            (p.get("nz", 1) if p["ndim"] == 3 else 1))
 
 
 def coords(n):
@@ -50,18 +53,23 @@ def coords(n):
     return np.arange(1, n + 1, dtype=np.float64) / (n + 1)
 
 
-def sine_mode(p, mode_p, mode_q=1, amplitude=1.0):
-    """amplitude * sin(p pi x) sin(q pi y) on the interior grid (1D: sin(p pi x))."""
+def sine_mode(p, mode_p, mode_q=1, amplitude=1.0, mode_s=1):
+    """amplitude * sin(p pi x) sin(q pi y) [sin(s pi z)] on the interior grid (1D:
+    sin(p pi x))."""
     x = coords(p["nx"])
     fx = np.sin(mode_p * np.pi * x)
     if p["ndim"] == 1:
         return amplitude * fx
     y = coords(p["ny"])
     fy = np.sin(mode_q * np.pi * y)
-    return amplitude * np.outer(fy, fx).reshape(-1)
+    f2 = np.outer(fy, fx).reshape(-1)
+    if p["ndim"] == 2:
+        return amplitude * f2
+    fz = np.sin(mode_s * np.pi * coords(p["nz"]))
+    return amplitude * np.outer(fz, f2).reshape(-1)
 
 
-def gaussian(p, seed, sigma=0.1, centre=(0.5, 0.5), noise=1e-3):
+def gaussian(p, seed, sigma=0.1, centre=(0.5, 0.5, 0.5), noise=1e-3):
     """exp(-|x - c|^2 / (2 sigma^2)) plus seeded uniform noise in [-noise, noise]."""
     rng = np.random.default_rng(seed)
     x = coords(p["nx"])
@@ -69,9 +77,14 @@ def gaussian(p, seed, sigma=0.1, centre=(0.5, 0.5), noise=1e-3):
         g = np.exp(-((x - centre[0]) ** 2) / (2 * sigma * sigma))
         return g + rng.uniform(-noise, noise, size=p["nx"])
     y = coords(p["ny"])
-    g = np.exp(-((x[None, :] - centre[0]) ** 2 + (y[:, None] - centre[1]) ** 2)
-               / (2 * sigma * sigma))
-    return (g + rng.uniform(-noise, noise, size=(p["ny"], p["nx"]))).reshape(-1)
+    if p["ndim"] == 2:
+        g = np.exp(-((x[None, :] - centre[0]) ** 2 + (y[:, None] - centre[1]) ** 2)
+                   / (2 * sigma * sigma))
+        return (g + rng.uniform(-noise, noise, size=(p["ny"], p["nx"]))).reshape(-1)
+    z = coords(p["nz"])
+    g = np.exp(-((x[None, None, :] - centre[0]) ** 2 + (y[None, :, None] - centre[1]) ** 2
+                 + (z[:, None, None] - centre[2]) ** 2) / (2 * sigma * sigma))
+    return (g + rng.uniform(-noise, noise, size=(p["nz"], p["ny"], p["nx"]))).reshape(-1)
 
 
 def uniform_field(p, seed, lo=0.0, hi=0.1):
@@ -158,3 +171,19 @@ def paper_fig3(gamma, mem=None):
     u0[10, 10] = 10.0
     return {"name": "paper_fig3_g%g" % gamma, "problem": p,
             "memory": mem or memory("full"), "u0": u0.reshape(-1), "nsteps": 1500}
+
+
+def superdiffusion_2d(n=256, nsteps=20000, gamma=1.5):
+    """Superdiffusion (gamma in (1, 2]): 2D 256^2, gamma 1.5, alpha 1, no reaction,
+    Gaussian sigma 0.1 + U(+-1e-3) (seed 6), r = 0.1, 20000 steps, full memory."""
+    p = problem(2, n, gamma, 1.0, 0.1)
+    return {"name": "2d_n%d_g%g_super_full" % (n, gamma), "problem": p,
+            "memory": memory("full"), "u0": gaussian(p, 6), "nsteps": nsteps}
+
+
+def diffusion_3d(n=64, nsteps=20000):
+    """3D 64^3 (7-point stencil), gamma 0.8, alpha 1, f = -0.1 u, Gaussian sigma 0.1 +
+    U(+-1e-3) (seed 7), r = 0.05, 20000 steps, full memory."""
+    p = problem(3, n, 0.8, 1.0, 0.05, rxn="linear", rate=0.1)
+    return {"name": "3d_n%d_g0.8_full" % n, "problem": p, "memory": memory("full"),
+            "u0": gaussian(p, 7), "nsteps": nsteps}

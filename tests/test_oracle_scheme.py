@@ -1,9 +1,10 @@
 """Pins of the oracle's scheme, eq. (21) with the memory modes of eqs. (22), (24):
-gamma = 1 is classical FTCS diffusion (a sparse-matrix textbook scheme), a discrete
-sine mode is an eigenvector (the PDE reduces to a scalar recursion), the scalar
-recursion converges to Mittag-Leffler relaxation at first order, the GL weights
-reproduce the closed-form fractional derivative of t^p, and the degenerate memory
-settings reproduce full memory bit for bit."""
+gamma = 1 is classical FTCS diffusion (a sparse-matrix textbook scheme), gamma = 2 is the
+classical leapfrog scheme of the wave equation, a discrete sine mode is an eigenvector
+(the PDE reduces to a scalar recursion), the scalar recursion converges to Mittag-Leffler
+relaxation at first order (sub- and superdiffusion), the GL weights reproduce the
+closed-form fractional derivative (and integral) of t^p, and the degenerate memory
+settings reproduce full memory bit for bit.  1D, 2D and 3D grids."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -18,7 +19,12 @@ def lap_matrix(p):
         return sp.diags([np.ones(n - 1), -2 * np.ones(n), np.ones(n - 1)], [-1, 0, 1])
     if p["ndim"] == 1:
         return d2(p["nx"]).tocsr()
-    return (sp.kron(sp.identity(p["ny"]), d2(p["nx"])) + sp.kron(d2(p["ny"]), sp.identity(p["nx"]))).tocsr()
+    L2 = sp.kron(sp.identity(p["ny"]), d2(p["nx"])) + sp.kron(d2(p["ny"]), sp.identity(p["nx"]))
+    if p["ndim"] == 2:
+        return L2.tocsr()
+    # 3D, x fastest then y then z: the 2D operator on every z layer plus the z coupling
+    return (sp.kron(sp.identity(p["nz"]), L2) +
+            sp.kron(d2(p["nz"]), sp.identity(p["nx"] * p["ny"]))).tocsr()
 
 
 def ftcs(p, u0, n):
@@ -41,9 +47,10 @@ def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("ndim,rxn", [(1, "none"), (2, "linear"), (2, "fisher")])
+@pytest.mark.parametrize("ndim,rxn", [(1, "none"), (2, "linear"), (2, "fisher"), (3, "fisher")])
 def test_gamma_one_is_ftcs(ndim, rxn):
-    p = W.problem(ndim, 24, 1.0, 0.7, 0.2, rxn=rxn, rate=0.3)
+    p = W.problem(ndim, 24 if ndim < 3 else 11, 1.0, 0.7, 0.2 if ndim < 3 else 0.1, rxn=rxn,
+                  rate=0.3)
     u0 = W.gaussian(p, 11) + 0.2
     n = 300
     got = oracle.run(p, W.memory("full"), u0, n)
@@ -55,13 +62,15 @@ MEMS = [W.memory("full"), W.memory("short", L=7), W.memory("adaptive", a=2),
 
 
 @pytest.mark.parametrize("mem", MEMS, ids=lambda m: "%s-%s-%d" % (m["mode"], m["rule"], m["a"]))
-@pytest.mark.parametrize("ndim,pq", [(1, (1, 1)), (1, (5, 1)), (2, (1, 1)), (2, (2, 3))])
+@pytest.mark.parametrize("ndim,pq", [(1, (1, 1, 1)), (1, (5, 1, 1)), (2, (1, 1, 1)),
+                                     (2, (2, 3, 1)), (3, (1, 1, 1)), (3, (2, 1, 3))])
 def test_sine_mode_is_an_eigenvector(mem, ndim, pq):
-    p = W.problem(ndim, 15, 0.7, 1.0, 0.08, rxn="linear", rate=0.5)
+    p = W.problem(ndim, 15 if ndim < 3 else 7, 0.7, 1.0, 0.08 if ndim < 3 else 0.05,
+                  rxn="linear", rate=0.5)
     n = 250
-    phi = W.sine_mode(p, *pq)
+    phi = W.sine_mode(p, pq[0], pq[1], mode_s=pq[2])
     U = oracle.run(p, mem, 0.8 * phi, n, store_all=True)
-    v = oracle.mode_run(p, mem, pq[0], pq[1], 0.8, n)
+    v = oracle.mode_run(p, mem, pq[0], pq[1], 0.8, n, s=pq[2])
     err = np.abs(U - np.outer(v, phi)).max()
     assert err < 1e-13 * np.abs(U).max()
 
@@ -74,11 +83,14 @@ def mittag_leffler(gamma, z):
     return float(np.sum((-z) ** j / special.gamma(gamma * j + 1)))
 
 
-@pytest.mark.parametrize("gamma,T", [(0.5, 0.01), (0.8, 0.05), (0.65, 0.03)])
+@pytest.mark.parametrize("gamma,T", [(0.5, 0.01), (0.8, 0.05), (0.65, 0.03),
+                                     (1.3, 0.2), (1.7, 0.3), (2.0, 0.4)])
 def test_mode_recursion_converges_to_mittag_leffler(gamma, T):
     # du/dt = alpha D^(1-gamma) Lap u on one eigenmode is Caputo relaxation
     # d^gamma v/dt^gamma = -alpha lam v, solved by v(t) = E_gamma(-alpha lam t^gamma);
-    # the explicit GL scheme is first order in dt.
+    # the explicit GL scheme is first order in dt.  For 1 < gamma <= 2, D^(1-gamma) is the
+    # fractional integral of order gamma - 1 and the same holds with v'(0) = 0 (at gamma = 2,
+    # E_2(-z) = cos(sqrt(z))).
     nx = 7
     dx = 1.0 / (nx + 1)
     lam = 4 * np.sin(np.pi / (2 * (nx + 1))) ** 2 / dx ** 2
@@ -104,11 +116,12 @@ def test_cfg1_mode_matches_mittag_leffler():
     assert rel(u, amp * w["u0"]) < 2e-6
 
 
-@pytest.mark.parametrize("gamma", [0.3, 0.5, 0.8])
+@pytest.mark.parametrize("gamma", [0.3, 0.5, 0.8, 1.3, 1.7])
 @pytest.mark.parametrize("q", [1, 2, 3])
 def test_gl_weights_reproduce_derivative_of_power(gamma, q):
     # h^-nu sum_{m=0}^{k} psi(gamma,m) f(t - m h) -> D^nu t^q = Gamma(q+1)/Gamma(q+1-nu) t^(q-nu),
-    # nu = 1 - gamma, with first-order convergence in h (eqs. 5, 7).
+    # nu = 1 - gamma, with first-order convergence in h (eqs. 5, 7); for gamma > 1, nu < 0
+    # and the same sum is the GL fractional integral of order -nu.
     nu = 1.0 - gamma
     exact = special.gamma(q + 1) / special.gamma(q + 1 - nu)
     errs = []
@@ -194,3 +207,61 @@ def test_history_sum_against_closed_form_weights(golden_dir):
     full = oracle.history_sum(gamma, W.memory("full"), k, np.ones((k + 1, 4), np.float32))
     ref_full = np.exp(special.gammaln(k + gamma) - special.gammaln(gamma) - special.gammaln(k + 1))
     np.testing.assert_allclose(full, ref_full, rtol=1e-12)
+
+
+@pytest.mark.parametrize("gamma", [1.2, 1.4, 1.8, 2.0])
+def test_stability_bound_superdiffusion(gamma):
+    # The same bound r lam_max <= 2^gamma for 1 < gamma <= 2: on |z| = 1 the characteristic
+    # equation z (1 - 1/z)^gamma = -r lam has its only real positive solution at z = -1.  The
+    # amplitude may overshoot 1 (the solutions oscillate), so bounded means below 10.
+    nx = 31
+    lam_max = 4 * np.sin(nx * np.pi / (2 * (nx + 1))) ** 2
+    for factor, bounded in ((0.97, True), (1.03, False)):
+        r = factor * 2 ** gamma / lam_max
+        p = W.problem(1, nx, gamma, 1.0, r)
+        with np.errstate(over="ignore", invalid="ignore"):
+            v = oracle.mode_run(p, W.memory("full"), nx, 1, 1.0, 3000)
+            grown = not np.all(np.abs(v) < 10.0)
+        assert grown != bounded, (factor, np.abs(v).max())
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_gamma_two_is_leapfrog_wave(ndim):
+    # psi(2, m) = 1: u[k+1] - u[k] = r sum_{j<=k} delta[j], so u[k+1] - 2 u[k] + u[k-1] =
+    # r delta[k], the explicit central-difference wave scheme, started with u[1] = u[0] +
+    # r delta[0] (no reaction).
+    p = W.problem(ndim, 24 if ndim < 3 else 9, 2.0, 1.0, 0.9 / ndim)
+    u0 = W.gaussian(p, 12)
+    n = 200
+    L = lap_matrix(p)
+    r = p["alpha"] * p["dt"] ** 2 / p["dx"] ** 2
+    prev, cur = u0, u0 + r * (L @ u0)
+    for _ in range(n - 1):
+        prev, cur = cur, 2 * cur - prev + r * (L @ cur)
+    got = oracle.run(p, W.memory("full"), u0, n)
+    assert rel(got, cur) < 1e-11
+
+
+def test_gamma_two_mode_closed_form():
+    # On one sine mode the leapfrog recursion v[k+1] = (2 - r lam) v[k] - v[k-1], v[1] =
+    # (1 - r lam) v[0], has v[k] = cos((k + 1/2) theta) / cos(theta / 2) with
+    # cos(theta) = 1 - r lam / 2.
+    p = W.problem(2, 13, 2.0, 1.0, 0.45)
+    r = oracle.r_of(p)
+    lam = 4 * np.sin(3 * np.pi / 28) ** 2 + 4 * np.sin(5 * np.pi / 28) ** 2
+    theta = np.arccos(1 - r * lam / 2)
+    k = np.arange(1001)
+    v = oracle.mode_run(p, W.memory("full"), 3, 5, 1.0, 1000)
+    np.testing.assert_allclose(v, np.cos((k + 0.5) * theta) / np.cos(theta / 2), rtol=0,
+                               atol=1e-9)
+
+
+@pytest.mark.parametrize("ndim,shape", [(2, (13, 6, 1)), (3, (9, 7, 5))])
+def test_non_square_grids_are_ftcs_at_gamma_one(ndim, shape):
+    # Unequal sides catch an axis length or stride taken from the wrong side.
+    p = W.problem(ndim, shape[0], 1.0, 1.0, 0.1, rxn="linear", rate=0.2)
+    p.update(ny=shape[1], nz=shape[2])
+    rng = np.random.default_rng(21)
+    u0 = rng.uniform(0, 1, size=W.npoints(p))
+    n = 120
+    assert rel(oracle.run(p, W.memory("full"), u0, n), ftcs(p, u0, n)) < 1e-13

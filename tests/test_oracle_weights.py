@@ -9,6 +9,8 @@ from scipy import special
 import oracle
 
 GAMMAS = [0.3, 0.5, 0.6, 0.7, 0.8, 0.95]
+# superdiffusion: the same weights for 1 < gamma < 2 (the recurrence holds for any gamma)
+SUPER = [1.2, 1.5, 1.8]
 
 
 def psi_closed_form(gamma, n):
@@ -23,7 +25,7 @@ def psi_closed_form(gamma, n):
     return out
 
 
-@pytest.mark.parametrize("gamma", GAMMAS)
+@pytest.mark.parametrize("gamma", GAMMAS + SUPER)
 def test_psi_matches_gamma_function_closed_form(gamma):
     n = 50000
     ps = oracle.psi(gamma, n)
@@ -32,7 +34,7 @@ def test_psi_matches_gamma_function_closed_form(gamma):
     assert rel.max() < 1e-9
 
 
-@pytest.mark.parametrize("gamma", GAMMAS)
+@pytest.mark.parametrize("gamma", GAMMAS + SUPER)
 def test_psi_small_m_matches_scipy_binomial(gamma):
     n = 30
     m = np.arange(n + 1)
@@ -46,7 +48,7 @@ def test_psi_exact_values_at_gamma_half(golden_dir):
     assert np.array_equal(ps[rows[:, 0].astype(int)], rows[:, 1])
 
 
-@pytest.mark.parametrize("gamma", GAMMAS)
+@pytest.mark.parametrize("gamma", GAMMAS + SUPER)
 def test_psi_partial_sums_closed_form(gamma):
     # sum_{j<=k} psi(j) is the k-th coefficient of (1-z)^(1-gamma)/(1-z) = (1-z)^(-gamma),
     # i.e. Gamma(k+gamma) / (Gamma(gamma) Gamma(k+1)).
@@ -57,7 +59,7 @@ def test_psi_partial_sums_closed_form(gamma):
     assert (np.abs(cs - ref) / ref).max() < 1e-9
 
 
-@pytest.mark.parametrize("gamma", GAMMAS)
+@pytest.mark.parametrize("gamma", GAMMAS + SUPER)
 def test_psi_generating_function(gamma):
     # sum_m psi(gamma, m) z^m = (1 - z)^(1 - gamma) for |z| < 1.
     for z in (-0.5, 0.3, 0.5):
@@ -82,7 +84,7 @@ def test_psi_gamma_one_is_classical_diffusion():
     assert ps[0] == 1.0 and np.all(ps[1:] == 0.0)
 
 
-@pytest.mark.parametrize("gamma", GAMMAS)
+@pytest.mark.parametrize("gamma", GAMMAS + SUPER)
 def test_dpsi_digamma_closed_form(gamma):
     # d/dgamma of prod_{i=1}^m (i-2+gamma)/i = psi * (digamma(m-1+gamma) - digamma(gamma-1))
     n = 20000
@@ -95,7 +97,7 @@ def test_dpsi_digamma_closed_form(gamma):
     assert np.all(np.abs(dps[1:] - ref) <= 1e-10 * np.abs(ref) + 1e-16)
 
 
-@pytest.mark.parametrize("gamma", GAMMAS)
+@pytest.mark.parametrize("gamma", GAMMAS + SUPER)
 def test_dpsi_central_difference(gamma):
     n, h = 3000, 1e-5
     fd = (oracle.psi(gamma + h, n) - oracle.psi(gamma - h, n)) / (2 * h)
@@ -108,3 +110,24 @@ def test_dpsi_at_gamma_one_is_harmonic():
     m = np.arange(1, 10001, dtype=np.float64)
     assert dps[0] == 0.0
     np.testing.assert_allclose(dps[1:], 1.0 / m, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("gamma", SUPER)
+def test_psi_superdiffusion_signs_and_decay(gamma):
+    # 1 - gamma < 0: (-1)^m binom(1 - gamma, m) = binom(gamma - 2 + m, m) > 0, decreasing in m,
+    # with the same asymptotics m^(gamma-2) / Gamma(gamma-1) and a divergent sum.
+    ps = oracle.psi(gamma, 5000)
+    assert ps[0] == 1.0
+    assert np.all(ps[1:] > 0)
+    assert np.all(np.diff(ps) < 0)
+    m = 5000.0
+    assert abs(ps[-1] / (m ** (gamma - 2) / special.gamma(gamma - 1)) - 1) < 2e-3
+
+
+def test_psi_gamma_two_is_all_ones():
+    # binom(-1, m) (-1)^m = 1; d psi / d gamma = psi * sum_{i<=m} 1/(i-2+gamma) = H_m at gamma 2
+    ps = oracle.psi(2.0, 1000)
+    assert np.all(ps == 1.0)
+    dps = oracle.dpsi(2.0, 1000)
+    m = np.arange(1, 1001, dtype=np.float64)
+    np.testing.assert_allclose(dps[1:], np.cumsum(1.0 / m), rtol=1e-12, atol=0)
