@@ -10,8 +10,9 @@
  *
  *   r        = alpha dt^gamma / dx^2
  *   psi      = (-1)^m binom(1 - gamma, m)           (Sec. 2.1, eqs. (8), (11), (12))
- *   delta[j] = 5-point (2D) or 3-point (1D) un-normalised Laplacian of u[j]
- *              with zero values outside the grid     (eq. (17), eq. (15))
+ *   delta[j] = 5-point (2D), 3-point (1D) or 7-point (3D) un-normalised
+ *              Laplacian of u[j] with zero values outside the grid
+ *              (eq. (17), eq. (15); 3D sums the same over a third axis)
  *   sched(k) = the memory mode's (offset m, multiplicity c) pairs:
  *              full memory   m = 0..k, c = 1          (eq. (21))
  *              short memory  m = 0..min(L, k), c = 1  (eq. (22), L in steps)
@@ -19,6 +20,8 @@
  *                            each sample weighted by its increment length
  *                            (Sec. 3.2, Def. 3.1, Def. 3.2, Prop. 3.1, eq. (24))
  *   f(u)     = 0, -rate u (eq. (18)), or rate u (1 - u) (Fisher-KPP).
+ *   0 < gamma <= 2: subdiffusion, diffusion (gamma = 1) and superdiffusion use
+ *   the same recurrence and scheme (Sec. 2.1); at gamma = 2 every weight is 1.
  *
  * The history of the stencil values delta[j] of every past step is kept in
  * device memory as FP32 rows (one row per step, as the sum of eq. (21) is
@@ -28,8 +31,9 @@
  * Conventions for every entry point:
  *  - All array arguments are DEVICE pointers (e.g. torch CUDA tensors on the
  *    current device), never retained after the call returns.  A grid with
- *    nx * ny points is stored u[l * nx + j], x1 index j fastest.  An ensemble
- *    concatenates the problems' grids in order.
+ *    nx * ny points is stored u[l * nx + j], x1 index j fastest; a 3D grid
+ *    u[(n * ny + l) * nx + j].  An ensemble concatenates the problems' grids
+ *    in order.
  *  - Work is enqueued on the stream given at gl_init (NULL = the null
  *    stream).  gl_init, gl_step_n, gl_adjoint and gl_free return after the
  *    work they enqueued has finished (they synchronise the stream).
@@ -90,13 +94,14 @@ typedef int32_t gl_status;
                                     read); the rest in FP64. Adaptive memory: GL_EUNSUPPORTED */
 
 typedef struct gl_problem {
-    int32_t ndim;     /* 1 or 2 */
+    int32_t ndim;     /* 1, 2 or 3 */
     int32_t nx;       /* interior points along x1, >= 1 */
     int32_t ny;       /* interior points along x2, >= 1 (ignored and taken as 1 in 1D) */
+    int32_t nz;       /* interior points along x3, >= 1 (ignored and taken as 1 below 3D) */
     int32_t rxn;      /* GL_RXN_* */
     double dx;        /* grid spacing, > 0 */
     double dt;        /* time step, > 0 */
-    double gamma;     /* anomalous exponent, 0 < gamma <= 1 */
+    double gamma;     /* anomalous exponent, 0 < gamma <= 2 */
     double alpha;     /* diffusivity, > 0 */
     double rxn_rate;  /* rate of the reaction term (finite) */
 } gl_problem;

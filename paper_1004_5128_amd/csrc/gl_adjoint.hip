@@ -38,7 +38,7 @@ __device__ __forceinline__ double adj_dfdrate(int rxn, double u) {
 
 __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
     const double *__restrict__ lam1, double *__restrict__ lam0, float *__restrict__ Mrow,
-    const double *__restrict__ partial, int nsplit, int64_t P, int ndim, int nx, int ny,
+    const double *__restrict__ partial, int nsplit, int64_t P, int ndim, int nx, int ny, int nz,
     double r, double dt, int rxn, double rate, const double *__restrict__ uk,
     const double *__restrict__ Sk, const double *__restrict__ Gk, double *__restrict__ grad) {
     __shared__ double red[3][kAdjThreads];
@@ -50,13 +50,23 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
             const double e = p + 1 < nx ? lam1[p + 1] : 0.0;
             const double w = p > 0 ? lam1[p - 1] : 0.0;
             lap = e - 2.0 * lam1[p] + w;
-        } else {
-            const int64_t x = p % nx, y = p / nx;
-            const double e = x + 1 < nx ? lam1[p + 1] : 0.0;
+        } else {  // at most 2^28 points: 32-bit coordinates
+            const uint32_t pp = (uint32_t)p, row = pp / (uint32_t)nx;
+            const uint32_t x = pp - row * (uint32_t)nx;
+            const uint32_t y = ndim == 2 ? row : row % (uint32_t)ny;
+            const double e = x + 1 < (uint32_t)nx ? lam1[p + 1] : 0.0;
             const double w = x > 0 ? lam1[p - 1] : 0.0;
-            const double n = y + 1 < ny ? lam1[p + nx] : 0.0;
+            const double n = y + 1 < (uint32_t)ny ? lam1[p + nx] : 0.0;
             const double s = y > 0 ? lam1[p - nx] : 0.0;
-            lap = e + w - 4.0 * lam1[p] + n + s;
+            if (ndim == 2) {
+                lap = e + w - 4.0 * lam1[p] + n + s;
+            } else {
+                const int64_t layer = (int64_t)nx * ny;
+                const uint32_t z = row / (uint32_t)ny;
+                const double up = z + 1 < (uint32_t)nz ? lam1[p + layer] : 0.0;
+                const double dn = z > 0 ? lam1[p - layer] : 0.0;
+                lap = e + w + n + s + up + dn - 6.0 * lam1[p];
+            }
         }
         const double mu = r * lap;
         double A = mu;
@@ -99,8 +109,8 @@ void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, 
                            const double *Gk, double *grad, hipStream_t s) {
     const gl_problem &p = pb.p;
     GL_LAUNCH(adjoint_update_kernel, dim3((unsigned)adjoint_groups(pb.P)), dim3(kAdjThreads), 0, s,
-              lam1, lam0, Mrow, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, pb.r, p.dt, p.rxn,
-              p.rxn_rate, uk, Sk, Gk, grad);
+              lam1, lam0, Mrow, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, p.nz, pb.r, p.dt,
+              p.rxn, p.rxn_rate, uk, Sk, Gk, grad);
 }
 
 // One workgroup: lane t sums entries t, t + 256, ... in order, then a fixed tree.

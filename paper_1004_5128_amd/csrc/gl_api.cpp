@@ -66,6 +66,8 @@ namespace {
 
 thread_local std::string g_thread_err;
 
+constexpr int64_t kMaxPoints = int64_t(1) << 28;  // per problem
+
 gl_status load_initial(gl_ctx *ctx, const double *u0);
 
 gl_status fail(gl_ctx *ctx, gl_status code, const char *fmt, ...) {
@@ -134,21 +136,25 @@ gl_status validate(const gl_problem *probs, int32_t nprob, const gl_options *opt
                     "gl_init: the Toeplitz path sums full or short memory (not adaptive)");
     for (int32_t i = 0; i < nprob; ++i) {
         const gl_problem &p = probs[i];
-        if (p.ndim != 1 && p.ndim != 2)
-            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: ndim must be 1 or 2", i);
-        if (p.nx < 1 || (p.ndim == 2 && p.ny < 1))
+        if (p.ndim < 1 || p.ndim > 3)
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: ndim must be 1, 2 or 3", i);
+        if (p.nx < 1 || (p.ndim >= 2 && p.ny < 1) || (p.ndim == 3 && p.nz < 1))
             return fail(nullptr, GL_EINVAL, "gl_init: problem %d: grid must have >= 1 point", i);
+        // kernels address a problem's points with 32-bit byte offsets
+        if ((int64_t)p.nx * (p.ndim >= 2 ? p.ny : 1) * (p.ndim == 3 ? p.nz : 1) > kMaxPoints)
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: more than 2^28 grid points", i);
         if (!(p.dx > 0) || !std::isfinite(p.dx) || !(p.dt > 0) || !std::isfinite(p.dt))
             return fail(nullptr, GL_EINVAL, "gl_init: problem %d: dx and dt must be > 0", i);
-        if (!(p.gamma > 0.0 && p.gamma <= 1.0))
-            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: gamma must be in (0, 1]", i);
+        if (!(p.gamma > 0.0 && p.gamma <= 2.0))
+            return fail(nullptr, GL_EINVAL, "gl_init: problem %d: gamma must be in (0, 2]", i);
         if (!(p.alpha > 0.0) || !std::isfinite(p.alpha))
             return fail(nullptr, GL_EINVAL, "gl_init: problem %d: alpha must be > 0", i);
         if (p.rxn < GL_RXN_NONE || p.rxn > GL_RXN_FISHER || !std::isfinite(p.rxn_rate))
             return fail(nullptr, GL_EINVAL, "gl_init: problem %d: bad reaction", i);
         const double r = p.alpha * std::pow(p.dt, p.gamma) / (p.dx * p.dx);
         // von Neumann bound of the explicit scheme: the highest grid mode has
-        // Lap eigenvalue -> -4 ndim, and sum psi (-1)^m = 2^(1 - gamma).
+        // Lap eigenvalue -> -4 ndim, and sum psi (-1)^m = 2^(1 - gamma); for 1 < gamma <= 2
+        // the characteristic roots still leave the unit circle only through z = -1.
         if (r * 4.0 * p.ndim > std::pow(2.0, p.gamma) * (1.0 + 1e-12))
             return fail(nullptr, GL_EUNSTABLE,
                         "gl_init: problem %d: r = %.6g exceeds the stability bound 2^gamma/(4 "
@@ -223,7 +229,8 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
         gl::Problem &pb = ctx->probs[i];
         pb.p = probs[i];
         if (pb.p.ndim == 1) pb.p.ny = 1;
-        pb.P = (int64_t)pb.p.nx * pb.p.ny;
+        if (pb.p.ndim != 3) pb.p.nz = 1;
+        pb.P = (int64_t)pb.p.nx * pb.p.ny * pb.p.nz;
         pb.ld = round_up(pb.P, 64);
         pb.r = pb.p.alpha * std::pow(pb.p.dt, pb.p.gamma) / (pb.p.dx * pb.p.dx);
         pb.offset = ctx->total_points;
@@ -335,6 +342,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
         e.ndim = pb.p.ndim;
         e.nx = pb.p.nx;
         e.ny = pb.p.ny;
+        e.nz = pb.p.nz;
         e.rxn = pb.p.rxn;
         e.r = pb.r;
         e.dt = pb.p.dt;
@@ -535,6 +543,9 @@ gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
             return st;
         pb.old2_k1 = k1;
     }
+    if (pb.p.ndim == 3 && s > gl::kMaxFuse3)
+        return fail(ctx, GL_EINVAL, "blocked path: %lld steps per launch on a 3D grid (at most %d)",
+                    (long long)s, gl::kMaxFuse3);
     gl::BlockStepArgs args{};
     args.psi = pb.psi_blk;
     args.H = pb.H;
@@ -543,6 +554,7 @@ gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
     args.ndim = pb.p.ndim;
     args.nx = pb.p.nx;
     args.ny = pb.p.ny;
+    args.nz = pb.p.nz;
     args.rxn = pb.p.rxn;
     args.r = pb.r;
     args.dt = pb.p.dt;
@@ -745,6 +757,8 @@ gl_status gl_init(const gl_problem *probs, int32_t nprob, const gl_options *opt,
     if (const char *v = env_value("GL_SUBBLOCK")) ctx->tune.sub_B = std::atol(v);
     if (const char *v = env_value("GL_FUSE"))
         ctx->tune.fuse = std::min<int64_t>(gl::kMaxFuse, std::max(1L, std::atol(v)));
+    for (int32_t i = 0; i < nprob; ++i)  // 3D tiles take fewer steps per in-block launch
+        if (probs[i].ndim == 3) ctx->tune.fuse = std::min<int64_t>(ctx->tune.fuse, gl::kMaxFuse3);
     if (const char *v = env_value("GL_TOEPLITZ_KCHUNK"))
         ctx->tune.kchunk = std::max<int64_t>(gl::kMaxTK, std::atol(v) / gl::kMaxTK * gl::kMaxTK);
     ctx->stream = static_cast<hipStream_t>(opt->stream);

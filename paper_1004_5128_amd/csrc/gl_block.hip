@@ -12,7 +12,7 @@
 // over their sum Old + Old2 as one array.
 //
 // One launch takes s steps k .. k+s-1 of a sub-block.  A workgroup owns a tile of points
-// (16 x 16 in 2D, 256 in 1D) and recomputes a halo around it: step i is evaluated on the
+// (16 x 16 in 2D, 256 in 1D, 8 x 8 x 4 in 3D) and recomputes a halo around it: step i is evaluated on the
 // tile widened by S-1-i points (S >= s, the compile-time halo), which needs u[k+i] one point
 // further out, so u[k] is read on the tile widened by S and the states stay in LDS from step
 // to step.  The delta rows of the launch's own steps stay in the registers of the lane that
@@ -41,14 +41,22 @@ constexpr int kTile1 = 256;  // 1D tile length
 constexpr int kRowBatch = 32; // history rows loaded together (and the most a carry sums)
 constexpr int kWin = 16;      // rows per weight window
 constexpr int kTilePts = 256; // points of a tile
+constexpr int kTile3x = 8, kTile3y = 8, kTile3z = 4;  // 3D tile
+static_assert(kTile3x * kTile3y * kTile3z == kTilePts && kTile2 * kTile2 == kTilePts &&
+                  kTile1 == kTilePts, "every tile has kTilePts points");
 
-template <int S>
+// Region sizes for halo S: the u region (tile widened by S) and the step-0 region (widened
+// by S - 1).  1D and 2D share one instantiation sized for 2D; 3D has its own.
+template <int S, bool D3>
 struct StepGeom {
-    static constexpr int kUSide = kTile2 + 2 * S;                 // 2D u region side
-    static constexpr int kULen = kUSide * kUSide;                 // >= kTile1 + 2 S
-    static constexpr int kR0 = (kTile2 + 2 * (S - 1)) * (kTile2 + 2 * (S - 1));  // >= 1D's
-    static constexpr int kPts = (kR0 + kStepThreads - 1) / kStepThreads;       // per lane
-    static_assert(kULen >= kTile1 + 2 * S && kR0 >= kTile1 + 2 * (S - 1), "1D fits 2D sizes");
+    static constexpr int kULen = D3 ? (kTile3x + 2 * S) * (kTile3y + 2 * S) * (kTile3z + 2 * S)
+                                    : (kTile2 + 2 * S) * (kTile2 + 2 * S);
+    static constexpr int kR0 =
+        D3 ? (kTile3x + 2 * (S - 1)) * (kTile3y + 2 * (S - 1)) * (kTile3z + 2 * (S - 1))
+           : (kTile2 + 2 * (S - 1)) * (kTile2 + 2 * (S - 1));
+    static constexpr int kPts = (kR0 + kStepThreads - 1) / kStepThreads;  // per lane
+    static_assert(D3 || (kULen >= kTile1 + 2 * S && kR0 >= kTile1 + 2 * (S - 1)),
+                  "1D fits 2D sizes");
 };
 
 // Workgroups are dispatched to the 8 XCDs in turn (id mod 8), each XCD with its own L2.
@@ -68,22 +76,30 @@ __device__ __forceinline__ double step_reaction(int rxn, double rate, double u) 
     return 0.0;
 }
 
-template <int S>
+template <int S, bool D3>
 __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs a) {
-    using G = StepGeom<S>;
+    using G = StepGeom<S, D3>;
     __shared__ double lu[2][G::kULen];
     __shared__ float lrows[kRowBatch][kTilePts];  // carry: the tile's rows k1 .. k+s-1
     __shared__ double lpsi[kRowBatch + 2 * kMaxFuse];  // carry: psi(0 ..)
     const int tid = threadIdx.x;
-    const bool two = a.ndim == 2;
-    const int tx = two ? kTile2 : kTile1, ty = two ? kTile2 : 1, hy = two ? 1 : 0;
-    const int uw = tx + 2 * S, uh = ty + 2 * S * hy;              // u region
-    const int w0 = tx + 2 * (S - 1), h0 = ty + 2 * (S - 1) * hy;  // step-0 region
-    const int64_t nx = a.nx, ny = two ? a.ny : 1, P = a.P;
-    const int ntx = (int)((nx + tx - 1) / tx);
+    const bool two = !D3 && a.ndim == 2;
+    const int tx = D3 ? kTile3x : two ? kTile2 : kTile1;
+    const int ty = D3 ? kTile3y : two ? kTile2 : 1, tz = D3 ? kTile3z : 1;
+    const int hy = D3 || two ? 1 : 0;  // halo along y (and, in 3D, z)
+    constexpr int hz = D3 ? 1 : 0;
+    const int uw = tx + 2 * S, uh = ty + 2 * S * hy, ud = tz + 2 * S * hz;  // u region
+    const int w0 = tx + 2 * (S - 1), h0 = ty + 2 * (S - 1) * hy;            // step-0 region
+    const int d0 = tz + 2 * (S - 1) * hz;
+    const int uwh = uw * uh, w0h0 = w0 * h0;
+    const int64_t nx = a.nx, ny = hy ? a.ny : 1, nz = D3 ? a.nz : 1, P = a.P;
+    const int ntx = (int)((nx + tx - 1) / tx), nty = (int)((ny + ty - 1) / ty);
     const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int64_t gx0 = (int64_t)(two ? tile % ntx : tile) * tx - S;
-    const int64_t gy0 = two ? (int64_t)(tile / ntx) * ty - S : 0;
+    const int tix = tile % ntx, trest = tile / ntx;  // tile coordinates, x fastest
+    const int tiy = D3 ? trest % nty : trest, tiz = D3 ? trest / nty : 0;
+    const int64_t gx0 = (int64_t)tix * tx - S;
+    const int64_t gy0 = (int64_t)tiy * ty - S * hy;
+    const int64_t gz0 = (int64_t)tiz * tz - S * hz;
     const int s = a.s;
     const int64_t k = a.k;
     const bool from_carry = a.carry_in != nullptr;
@@ -97,9 +113,11 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
 #pragma unroll
     for (int c = 0; c < kULoads; ++c) {
         const int idx = tid + c * kStepThreads;
-        const int64_t gx = gx0 + idx % uw, gy = gy0 + idx / uw;
-        uin[c] = idx < uw * uh && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-        uv[c] = a.u_cur[uin[c] ? gy * nx + gx : 0];
+        const int iz = D3 ? idx / uwh : 0, ixy = idx - iz * uwh;
+        const int64_t gx = gx0 + ixy % uw, gy = gy0 + ixy / uw, gz = gz0 + iz;
+        uin[c] = idx < uwh * ud && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 &&
+                 gz < nz;
+        uv[c] = a.u_cur[uin[c] ? (gz * ny + gy) * nx + gx : 0];
     }
 
     // the lane's points: slot n is point tid + n * 256 of the step-0 region
@@ -111,23 +129,27 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
 #pragma unroll
     for (int n = 0; n < G::kPts; ++n) {
         const int r = tid + n * kStepThreads;
-        const int rx = r % w0, ry = r / w0;
-        const int64_t gx = gx0 + rx + 1, gy = gy0 + ry + hy;
-        const bool ok = r < w0 * h0 && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+        const int rz = D3 ? r / w0h0 : 0, rxy = r - rz * w0h0;
+        const int rx = rxy % w0, ry = rxy / w0;
+        const int64_t gx = gx0 + rx + 1, gy = gy0 + ry + hy, gz = gz0 + rz + hz;
+        const bool ok = r < w0h0 * d0 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 &&
+                        gz < nz;
         int l = min(rx, w0 - 1 - rx);
-        if (two) l = min(l, min(ry, h0 - 1 - ry));
+        if (hy) l = min(l, min(ry, h0 - 1 - ry));
+        if (D3) l = min(l, min(rz, d0 - 1 - rz));
         lvl[n] = ok ? l : -1;
-        ux[n] = (ry + hy) * uw + rx + 1;
-        tl[n] = (rx - (S - 1)) + (ry - (S - 1) * hy) * tx;
-        q[n] = ok ? gy * nx + gx : 0;
+        ux[n] = ((rz + hz) * uh + ry + hy) * uw + rx + 1;
+        tl[n] = (rx - (S - 1)) + (ry - (S - 1) * hy) * tx + (rz - (S - 1) * hz) * tx * ty;
+        q[n] = ok ? (gz * ny + gy) * nx + gx : 0;
     }
     // carry work: lane t continues, for tile point pt = t mod 256 (x fastest), the chains of
     // the next launch's steps 2 cp and 2 cp + 1, cp = t / 256 (uniform per wave)
     static_assert(kStepThreads == 4 * kTilePts && kMaxFuse == 8, "four step pairs per point");
     const int pt = tid % kTilePts, cp = tid / kTilePts;
-    const int64_t cgx = gx0 + S + pt % tx, cgy = gy0 + S * hy + pt / tx;
-    const bool cok = to_carry && cgx < nx && cgy < ny;
-    const int64_t cq = cok ? cgy * nx + cgx : 0;
+    const int64_t cgx = gx0 + S + pt % tx, cgy = gy0 + S * hy + (pt / tx) % ty;
+    const int64_t cgz = gz0 + S * hz + pt / (tx * ty);
+    const bool cok = to_carry && cgx < nx && cgy < ny && cgz < nz;
+    const int64_t cq = cok ? (cgz * ny + cgy) * nx + cgx : 0;
 
     // Chains of the s steps up to row k - 1: Old + Old2, then the sub-block's rows.  All loads
     // are issued before any is used and are unconditional: slots without a grid point read
@@ -232,7 +254,7 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
 #pragma unroll
     for (int c = 0; c < kULoads; ++c) {
         const int idx = tid + c * kStepThreads;
-        if (idx < uw * uh) {
+        if (idx < uwh * ud) {
             lu[0][idx] = uin[c] ? uv[c] : 0.0;
             lu[1][idx] = 0.0;
         }
@@ -268,8 +290,11 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
             if (lvl[n] < i) continue;
             const int x = ux[n];
             const double u = uc[x];
-            const double d = two ? uc[x + 1] + uc[x - 1] - 4.0 * u + uc[x + uw] + uc[x - uw]
-                                 : uc[x + 1] - 2.0 * u + uc[x - 1];
+            const double d =
+                D3    ? uc[x + 1] + uc[x - 1] + uc[x + uw] + uc[x - uw] + uc[x + uwh] +
+                            uc[x - uwh] - 6.0 * u
+                : two ? uc[x + 1] + uc[x - 1] - 4.0 * u + uc[x + uw] + uc[x - uw]
+                      : uc[x + 1] - 2.0 * u + uc[x - 1];
             double c = acc[n][i];
 #pragma unroll
             for (int i2 = 0; i2 < i; ++i2) c = fma(wl[i - i2], (double)dl[n][i2], c);
@@ -322,18 +347,27 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
 }
 
 void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
-    const int64_t ntiles = args.ndim == 2
-                               ? ((args.nx + kTile2 - 1) / kTile2) * ((args.ny + kTile2 - 1) / kTile2)
-                               : (args.nx + kTile1 - 1) / kTile1;
+    const int64_t ntiles =
+        args.ndim == 3   ? ((args.nx + kTile3x - 1) / kTile3x) * ((args.ny + kTile3y - 1) / kTile3y) *
+                             ((args.nz + kTile3z - 1) / kTile3z)
+        : args.ndim == 2 ? ((args.nx + kTile2 - 1) / kTile2) * ((args.ny + kTile2 - 1) / kTile2)
+                         : (args.nx + kTile1 - 1) / kTile1;
     const dim3 grid((unsigned)ntiles), block(kStepThreads);
-    if (args.s <= 1)
-        GL_LAUNCH(block_steps_kernel<1>, grid, block, 0, s, args);
-    else if (args.s <= 2)
-        GL_LAUNCH(block_steps_kernel<2>, grid, block, 0, s, args);
-    else if (args.s <= 4)
-        GL_LAUNCH(block_steps_kernel<4>, grid, block, 0, s, args);
-    else
-        GL_LAUNCH(block_steps_kernel<8>, grid, block, 0, s, args);
+    static_assert(kMaxFuse3 == 2, "3D instantiations");
+    if (args.ndim == 3) {  // s <= kMaxFuse3, checked by the caller
+        if (args.s <= 1)
+            GL_LAUNCH((block_steps_kernel<1, true>), grid, block, 0, s, args);
+        else
+            GL_LAUNCH((block_steps_kernel<2, true>), grid, block, 0, s, args);
+    } else if (args.s <= 1) {
+        GL_LAUNCH((block_steps_kernel<1, false>), grid, block, 0, s, args);
+    } else if (args.s <= 2) {
+        GL_LAUNCH((block_steps_kernel<2, false>), grid, block, 0, s, args);
+    } else if (args.s <= 4) {
+        GL_LAUNCH((block_steps_kernel<4, false>), grid, block, 0, s, args);
+    } else {
+        GL_LAUNCH((block_steps_kernel<8, false>), grid, block, 0, s, args);
+    }
 }
 
 }  // namespace gl

@@ -115,7 +115,7 @@ struct BatchEntry {
     double *partial;  // this problem's GEMV partials, up to its split count x P
     double *snap;     // adjoint snapshots: u[k+1] goes to snap[(k+1)/C] when C divides k+1
     int64_t groups;   // this problem's GEMV workgroup target (Problem::gemv_groups)
-    int32_t ndim, nx, ny, rxn;
+    int32_t ndim, nx, ny, nz, rxn;
     double r, dt, rate;
 };
 
@@ -138,7 +138,7 @@ struct Tuning {
     int64_t kchunk = 0;          // history rows per Toeplitz product chunk (multiple of 128);
                                  // 0: per product, the fewest chunks that fill the GPU
     int64_t sub_B = 32;          // sub-block length of the blocked path (32 or 64; 0: off)
-    int64_t fuse = 8;            // in-block steps per launch (1 .. kMaxFuse)
+    int64_t fuse = 8;            // in-block steps per launch (1 .. kMaxFuse; kMaxFuse3 in 3D)
 };
 
 // ---- blocked Toeplitz path
@@ -170,7 +170,7 @@ struct BlockStepArgs {
     const double *psi;
     float *H;
     int64_t ld, P;
-    int32_t ndim, nx, ny, rxn;
+    int32_t ndim, nx, ny, nz, rxn;
     double r, dt, rate;
     // Sums over the rows before the sub-block: row pre_row + i belongs to step k + i.  The
     // block's product Old ([B x P], row b) in the first sub-block of a block, Old + the
@@ -203,6 +203,7 @@ struct BlockStepArgs {
 };
 
 constexpr int kMaxFuse = 8;
+constexpr int kMaxFuse3 = 2;  // 3D: the halo grows in three directions (4 would spill)
 
 // Steps k .. k + s - 1 of one sub-block as a single kernel (history sums over the
 // sub-block's rows, stencil, reaction, state update, history rows).  The result of every

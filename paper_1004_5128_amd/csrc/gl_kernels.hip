@@ -255,19 +255,28 @@ __device__ __forceinline__ double reaction(int rxn, double rate, double u) {
     return 0.0;
 }
 
+// delta of eq. (17) at point p (3-point in 1D, 7-point in 3D), zero outside the grid.  A
+// problem has at most 2^28 points, so the coordinates come from 32-bit divisions.
 __device__ __forceinline__ double stencil_at(const GL_GLOBAL double *__restrict__ u, int64_t p,
-                                             int ndim, int nx, int ny) {
+                                             int ndim, int nx, int ny, int nz) {
     if (ndim == 1) {
         const double e = p + 1 < nx ? u[p + 1] : 0.0;
         const double w = p > 0 ? u[p - 1] : 0.0;
         return e - 2.0 * u[p] + w;
     }
-    const int64_t x = p % nx, y = p / nx;
-    const double e = x + 1 < nx ? u[p + 1] : 0.0;
+    const uint32_t pp = (uint32_t)p, row = pp / (uint32_t)nx;
+    const uint32_t x = pp - row * (uint32_t)nx;
+    const uint32_t y = ndim == 2 ? row : row % (uint32_t)ny;
+    const double e = x + 1 < (uint32_t)nx ? u[p + 1] : 0.0;
     const double w = x > 0 ? u[p - 1] : 0.0;
-    const double n = y + 1 < ny ? u[p + nx] : 0.0;
+    const double n = y + 1 < (uint32_t)ny ? u[p + nx] : 0.0;
     const double s = y > 0 ? u[p - nx] : 0.0;
-    return e + w - 4.0 * u[p] + n + s;
+    if (ndim == 2) return e + w - 4.0 * u[p] + n + s;
+    const int64_t layer = (int64_t)nx * ny;
+    const uint32_t z = row / (uint32_t)ny;
+    const double up = z + 1 < (uint32_t)nz ? u[p + layer] : 0.0;
+    const double dn = z > 0 ? u[p - layer] : 0.0;
+    return e + w + n + s + up + dn - 6.0 * u[p];
 }
 
 // One point of the update; returns nothing, writes unew[p], Hk[p] (nullable), S_out[p]
@@ -279,8 +288,9 @@ __device__ __forceinline__ void update_point(const GL_GLOBAL double *__restrict_
                                              GL_GLOBAL double *__restrict__ S_out,
                                              const GL_GLOBAL double *__restrict__ partial,
                                              int nsplit, int64_t P, int ndim, int nx, int ny,
-                                             double r, double dt, int rxn, double rate, int64_t p) {
-    const double d = stencil_at(u, p, ndim, nx, ny);
+                                             int nz, double r, double dt, int rxn, double rate,
+                                             int64_t p) {
+    const double d = stencil_at(u, p, ndim, nx, ny, nz);
     double s = d;
     if (base) s += base[p];
     int q = 0;
@@ -301,19 +311,22 @@ __device__ __forceinline__ void update_point(const GL_GLOBAL double *__restrict_
 __global__ __launch_bounds__(256) void update_kernel(
     const double *__restrict__ u, const double *__restrict__ base, double *__restrict__ unew,
     float *__restrict__ Hk, double *__restrict__ S_out, const double *__restrict__ partial,
-    int nsplit, int64_t P, int ndim, int nx, int ny, double r, double dt, int rxn, double rate) {
+    int nsplit, int64_t P, int ndim, int nx, int ny, int nz, double r, double dt, int rxn,
+    double rate) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     update_point((const GL_GLOBAL double *)u, (const GL_GLOBAL double *)base,
                  (GL_GLOBAL double *)unew, (GL_GLOBAL float *)Hk, (GL_GLOBAL double *)S_out,
-                 (const GL_GLOBAL double *)partial, nsplit, P, ndim, nx, ny, r, dt, rxn, rate, p);
+                 (const GL_GLOBAL double *)partial, nsplit, P, ndim, nx, ny, nz, r, dt, rxn, rate,
+                 p);
 }
 
 void launch_update(const Problem &pb, const double *u, const double *base, double *unew,
                    float *Hk, double *S_out, const double *partial, int nsplit, hipStream_t s) {
     const gl_problem &p = pb.p;
     GL_LAUNCH(update_kernel, dim3((unsigned)((pb.P + 255) / 256)), dim3(256), 0, s, u, base, unew,
-              Hk, S_out, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, pb.r, p.dt, p.rxn, p.rxn_rate);
+              Hk, S_out, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, p.nz, pb.r, p.dt, p.rxn,
+              p.rxn_rate);
 }
 
 // Batched update: workgroups laid out problem after problem, ceil(P / 256) each.
@@ -334,7 +347,7 @@ __global__ __launch_bounds__(256) void update_batched_kernel(const BatchEntry *_
     const int nsplit = gemv_splits(terms, e.P, e.groups);
     update_point((const GL_GLOBAL double *)e.u[cur], nullptr, (GL_GLOBAL double *)e.u[cur ^ 1],
                  (GL_GLOBAL float *)e.H + k * e.ld, nullptr, (const GL_GLOBAL double *)e.partial,
-                 nsplit, e.P, e.ndim, e.nx, e.ny, e.r, e.dt, e.rxn, e.rate, p);
+                 nsplit, e.P, e.ndim, e.nx, e.ny, e.nz, e.r, e.dt, e.rxn, e.rate, p);
     if ((k + 1) % C == 0)  // adjoint checkpoint of u[k+1]
         ((GL_GLOBAL double *)e.snap)[((k + 1) / C) * e.P + p] = ((GL_GLOBAL double *)e.u[cur ^ 1])[p];
 }

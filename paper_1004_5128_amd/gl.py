@@ -38,8 +38,8 @@ STATUS_NAMES = {0: "GL_OK", -1: "GL_EINVAL", -2: "GL_EUNSTABLE", -3: "GL_ENOMEM"
 
 
 class gl_problem(C.Structure):
-    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("rxn", C.c_int32),
-                ("dx", C.c_double), ("dt", C.c_double), ("gamma", C.c_double),
+    _fields_ = [("ndim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("rxn", C.c_int32), ("dx", C.c_double), ("dt", C.c_double), ("gamma", C.c_double),
                 ("alpha", C.c_double), ("rxn_rate", C.c_double)]
 
 
@@ -179,8 +179,8 @@ def gl_history_sum(ctx, iprob, k, hist, ld, S):
 # ---------------------------------------------------------------- convenience
 
 def make_problem(d):
-    return gl_problem(int(d["ndim"]), int(d["nx"]), int(d.get("ny", 1)), GL_RXN[d.get("rxn", "none")],
-                      float(d["dx"]), float(d["dt"]), float(d["gamma"]), float(d["alpha"]),
+    return gl_problem(int(d["ndim"]), int(d["nx"]), int(d.get("ny", 1)), int(d.get("nz", 1)),
+                      GL_RXN[d.get("rxn", "none")], float(d["dx"]), float(d["dt"]), float(d["gamma"]), float(d["alpha"]),
                       float(d.get("rate", 0.0)))
 
 
@@ -196,7 +196,9 @@ def make_options(memory, max_steps, sum_path="gemv", block_B=0, check_finite=Fal
 
 
 def npoints(d):
-    return int(d["nx"]) * (int(d.get("ny", 1)) if int(d["ndim"]) == 2 else 1)
+    nd = int(d["ndim"])
+    return (int(d["nx"]) * (int(d.get("ny", 1)) if nd >= 2 else 1) *
+            (int(d.get("nz", 1)) if nd == 3 else 1))
 
 
 class Solver:

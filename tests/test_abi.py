@@ -57,7 +57,8 @@ def test_struct_layout_matches_c(tmp_path):
 #include <stddef.h>
 #include "gl.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\\n", sizeof(gl_problem), offsetof(gl_problem, dx),
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(gl_problem), offsetof(gl_problem, nz),
+         offsetof(gl_problem, dx),
          offsetof(gl_problem, rxn_rate), sizeof(gl_options), offsetof(gl_options, stream));
   printf("%zu %zu %zu\\n", offsetof(gl_options, short_L), offsetof(gl_options, max_steps),
          offsetof(gl_options, ckpt_every));
@@ -70,14 +71,15 @@ int main(void) {
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
                                            check=True).stdout.split()]
     from paper_1004_5128_amd.gl import gl_options, gl_problem
-    assert vals == [C.sizeof(gl_problem), gl_problem.dx.offset, gl_problem.rxn_rate.offset,
+    assert vals == [C.sizeof(gl_problem), gl_problem.nz.offset, gl_problem.dx.offset,
+                    gl_problem.rxn_rate.offset,
                     C.sizeof(gl_options), gl_options.stream.offset, gl_options.short_L.offset,
                     gl_options.max_steps.offset, gl_options.ckpt_every.offset]
 
 
 def _init(lib, prob_kw, opt_kw, nprob=1):
     from paper_1004_5128_amd.gl import gl_options, gl_problem
-    base = dict(ndim=2, nx=8, ny=8, rxn=0, dx=1 / 9, dt=1e-4, gamma=0.8, alpha=1.0, rxn_rate=0.0)
+    base = dict(ndim=2, nx=8, ny=8, nz=1, rxn=0, dx=1 / 9, dt=1e-4, gamma=0.8, alpha=1.0, rxn_rate=0.0)
     base.update(prob_kw)
     probs = (gl_problem * max(nprob, 1))(*[gl_problem(**base)] * max(nprob, 1))
     o = dict(mem_mode=0, adapt_rule=0, short_L=0, adapt_a=2, sum_path=0, block_B=0,
@@ -94,10 +96,13 @@ def _init(lib, prob_kw, opt_kw, nprob=1):
 
 
 @pytest.mark.parametrize("prob_kw,opt_kw,code", [
-    ({"ndim": 3}, {}, -1),
+    ({"ndim": 4}, {}, -1),
+    ({"ndim": 0}, {}, -1),
     ({"nx": 0}, {}, -1),
+    ({"ndim": 3, "nz": 0}, {}, -1),
+    ({"ndim": 3, "nx": 1024, "ny": 1024, "nz": 257}, {}, -1),   # more than 2^28 points
     ({"gamma": 0.0}, {}, -1),
-    ({"gamma": 1.2}, {}, -1),
+    ({"gamma": 2.01}, {}, -1),
     ({"alpha": -1.0}, {}, -1),
     ({"dt": 0.0}, {}, -1),
     ({"rxn": 7}, {}, -1),
@@ -108,6 +113,8 @@ def _init(lib, prob_kw, opt_kw, nprob=1):
     ({}, {"max_steps": 0}, -1),
     ({}, {"sum_path": 4}, -1),
     ({"dt": 1e-2}, {}, -2),       # r = 0.01^0.8 * 81 = 2.04 > 2^0.8 / 8
+    ({"ndim": 3, "nz": 8, "dt": 4.8e-4}, {}, -2),   # r = 0.179: under 2^0.8 / 8, over 2^0.8 / 12
+    ({"gamma": 1.5, "dt": 0.03}, {}, -2),           # r = 0.42 > 2^1.5 / 8
 ])
 def test_validation_errors(lib, prob_kw, opt_kw, code):
     st, msg, ctx = _init(lib, prob_kw, opt_kw)

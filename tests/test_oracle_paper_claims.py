@@ -93,3 +93,28 @@ def test_short_memory_falls_behind_as_gamma_nears_one():
         ratios.append(es / ea)
     assert all(r > 1 for r in ratios), ratios
     assert all(r1 < r2 for r1, r2 in zip(ratios, ratios[1:])), ratios
+
+
+def test_memory_approximations_break_down_in_superdiffusion():
+    # The Discussion expects much larger errors from both short and adaptive memory when
+    # superdiffusion makes the history oscillate.  On a 29 x 29 Gaussian (r = 0.05, f = -0.2 u,
+    # 600 steps) both approximations stay accurate at gamma = 0.7 and, for adaptive memory,
+    # at gamma = 1.3; at gamma = 1.7 and 2 the truncated or sampled sums no longer keep the
+    # scheme bounded and both errors exceed 100 %.
+    def errors(gamma):
+        p = W.problem(2, 29, gamma, 1.0, 0.05, rxn="linear", rate=0.2)
+        u0 = W.gaussian(p, 35)
+        full = oracle.run(p, W.memory("full"), u0, 600)
+        out = []
+        for mem in (W.memory("short", L=40), W.memory("adaptive", a=10)):
+            with np.errstate(over="ignore", invalid="ignore"):
+                u = oracle.run(p, mem, u0, 600)
+                out.append(float(np.linalg.norm(u - full) / np.linalg.norm(full)))
+        return out
+    s07, a07 = errors(0.7)
+    assert s07 < 0.3 and a07 < 1e-3
+    s13, a13 = errors(1.3)
+    assert a13 < 1e-3
+    for gamma in (1.7, 2.0):
+        s, a = errors(gamma)
+        assert not (s < 1.0) and not (a < 1.0), (gamma, s, a)
