@@ -39,9 +39,19 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+MODES3 = [(1, 1, 1), (1, 1, 3), (3, 1, 1), (1, 3, 3), (3, 3, 3)]
+
+
 def modal(u, p, modes):
+    """Sine-mode coefficients of a 2D or 3D field (discrete sine transform at the modes)."""
     from paper_1004_5128_amd import workloads as W
     x, y = W.coords(p["nx"]), W.coords(p["ny"])
+    if p["ndim"] == 3:
+        z = W.coords(p["nz"])
+        U = np.asarray(u).reshape(p["nz"], p["ny"], p["nx"])
+        return np.array([8.0 / ((p["nx"] + 1) * (p["ny"] + 1) * (p["nz"] + 1)) *
+                         np.einsum("k,j,i,kji->", np.sin(c * np.pi * z), np.sin(b * np.pi * y),
+                                   np.sin(a * np.pi * x), U) for a, b, c in modes])
     U = np.asarray(u).reshape(p["ny"], p["nx"])
     return np.array([4.0 / ((p["nx"] + 1) * (p["ny"] + 1)) *
                      (np.sin(b * np.pi * y) @ U @ np.sin(a * np.pi * x)) for a, b in modes])
@@ -181,26 +191,27 @@ def toeplitz_chunks(rows, BM, P):
     return -(-rows // kc) if rows > 0 else 0
 
 
-def fuse():
-    """In-block steps per launch (GL_FUSE, default 8)."""
+def fuse(ndim=2):
+    """In-block steps per launch (GL_FUSE, default 8; at most 2 on 3D grids)."""
     v = os.environ.get("GL_FUSE")
-    return min(8, max(1, int(v))) if v else 8
+    f = min(8, max(1, int(v))) if v else 8
+    return min(f, 2) if ndim == 3 else f
 
 
-def block_launches(n, B):
+def block_launches(n, B, ndim=2):
     """(first step, steps) of each in-block launch of an n-step run, as the library groups them:
     at most fuse() steps, never across a sub-block (a block with one level)."""
     B2 = sub_block(B)
     out, k = [], 0
     while k < n:
         left = B2 - (k % B) % B2 if B2 else B - k % B
-        s = max(1, min(fuse(), n - k, left))
+        s = max(1, min(fuse(ndim), n - k, left))
         out.append((k, s))
         k += s
     return out
 
 
-def algorithmic_work(path, P, n, B, terms):
+def algorithmic_work(path, P, n, B, terms, ndim=2):
     """Algorithmic work of each kernel over one solve of n steps (see the design notes):
      hist_gemv:  every history row of terms m >= 1 read once, 4 bytes per point
      update:     u[k] read, u[k+1] and the FP32 history row k written (20 bytes per point)
@@ -224,7 +235,7 @@ def algorithmic_work(path, P, n, B, terms):
         work["toeplitz_bytes"] = ("hbm", P * sum(4 * k0 + (8 * B if chunks(k0) == 1 else
                                                            4 * B * chunks(k0)) for k0 in blocks))
         tri = 0
-        for k, s in block_launches(n, B):
+        for k, s in block_launches(n, B, ndim):
             b = k % B
             b2 = b % B2 if B2 else b
             has_pre = k >= B or b - b2 > 0
@@ -259,7 +270,7 @@ def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
     B = block_B or 256
     terms = [s.schedule_terms(k) for k in range(n)]
     macs = P * sum(terms)
-    work = algorithmic_work(path, P, n, B, terms)
+    work = algorithmic_work(path, P, n, B, terms, p["ndim"])
     for i in range(warmup):
         log(path, "warmup", i)
         s.reset(u0)
@@ -419,6 +430,42 @@ def paper_fig3(reps=2):
           flush=True)
 
 
+def run_extra_workloads(block_B, with_oracle):
+    """Superdiffusion (2D 256^2, gamma 1.5) and a 3D grid (64^3, 7-point stencil), 20000 steps
+    each, full memory, on the blocked path: time per solve (one warmup, one timed), history
+    MACs/s, the dominant kernel's roofline from a profiled solve and, with the oracle, the
+    largest error of a few sine-mode coefficients at the last step against the oracle's mode
+    recursion, relative to the largest initial coefficient (the scale of the history terms)."""
+    from paper_1004_5128_amd import workloads as W
+    out = {}
+    for w, modes in ((W.superdiffusion_2d(), MODES), (W.diffusion_3d(), MODES3)):
+        p, n = w["problem"], w["nsteps"]
+        log("workload", w["name"])
+        r = run_path("toeplitz", w, 1, 1, block_B, prefix=False)
+        d = {"ms_per_solve": r["ms_per_step"], "history_macs_per_solve": r["macs"],
+             "value": r["macs"] / (r["ms_per_step"] / 1e3), "unit": "history MACs/s",
+             "grid": [p["nx"], p["ny"]] + ([p["nz"]] if p["ndim"] == 3 else []),
+             "gamma": p["gamma"], "time_steps": n}
+        kern = {}
+        for name, (cnt, ms) in r["prof"].items():
+            if cnt:
+                kern[name] = {"launches": cnt, "ms_per_solve": ms, "avg_us": ms * 1e3 / cnt}
+                if name in r["work"]:
+                    kind, work = r["work"][name]
+                    kern[name]["roofline"] = roofline_of(kind, work, cnt, ms)
+        d["kernels"] = kern
+        if with_oracle:
+            import oracle
+            c0 = modal(w["u0"], p, modes)
+            ref = np.array([c0[i] * oracle.mode_run(p, w["memory"], m[0], m[1], 1.0, n,
+                                                    s=m[2] if len(m) > 2 else 1)[-1]
+                            for i, m in enumerate(modes)])
+            d["modal_err_vs_oracle_full_length"] = float(
+                np.abs(modal(r["uT"], p, modes) - ref).max() / np.abs(c0).max())
+        out[w["name"]] = d
+    return out
+
+
 def probe_hipblaslt(reps=10):
     """Vendor BF16 GEMMs (torch.matmul -> hipBLASLt) on the same GPU for comparison: square
     4096..16384 and the block product's shape (256 x 19968) x (19968 x 65536)."""
@@ -452,6 +499,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the short / adaptive memory runs of the same workload")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the superdiffusion and 3D workloads")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 1 GiB device copy (reference for traffic counters)")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -564,6 +613,9 @@ def main():
         out_paths["memory_modes"]["full"] = {
             "path": "gemv" if "gemv" in res else primary,
             "ms_per_solve": full["ms_per_step"], "history_macs_per_solve": full["macs"]}
+
+    if not args.no_extra and not args.profile_steps:
+        out_paths["workloads"] = run_extra_workloads(args.block_B, not args.no_cpu)
 
     r = res[primary]
     # the dominant kernel of the headline path (largest share of the solve's time)

@@ -77,7 +77,7 @@ __device__ __forceinline__ double step_reaction(int rxn, double rate, double u) 
 }
 
 template <int S, bool D3>
-__global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs a) {
+__device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
     using G = StepGeom<S, D3>;
     __shared__ double lu[2][G::kULen];
     __shared__ float lrows[kRowBatch][kTilePts];  // carry: the tile's rows k1 .. k+s-1
@@ -346,6 +346,19 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
     }
 }
 
+template <int S>
+__global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs a) {
+    block_steps_body<S, false>(a);
+}
+
+// A 3D grid has four times the tiles of a 2D grid of the same size: at most 64 VGPRs
+// (eight waves per SIMD) keep two workgroups of 16 waves resident per CU.
+template <int S>
+__global__ __launch_bounds__(kStepThreads) __attribute__((amdgpu_waves_per_eu(8)))
+void block_steps_kernel_3d(BlockStepArgs a) {
+    block_steps_body<S, true>(a);
+}
+
 void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
     const int64_t ntiles =
         args.ndim == 3   ? ((args.nx + kTile3x - 1) / kTile3x) * ((args.ny + kTile3y - 1) / kTile3y) *
@@ -356,17 +369,17 @@ void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
     static_assert(kMaxFuse3 == 2, "3D instantiations");
     if (args.ndim == 3) {  // s <= kMaxFuse3, checked by the caller
         if (args.s <= 1)
-            GL_LAUNCH((block_steps_kernel<1, true>), grid, block, 0, s, args);
+            GL_LAUNCH(block_steps_kernel_3d<1>, grid, block, 0, s, args);
         else
-            GL_LAUNCH((block_steps_kernel<2, true>), grid, block, 0, s, args);
+            GL_LAUNCH(block_steps_kernel_3d<2>, grid, block, 0, s, args);
     } else if (args.s <= 1) {
-        GL_LAUNCH((block_steps_kernel<1, false>), grid, block, 0, s, args);
+        GL_LAUNCH(block_steps_kernel<1>, grid, block, 0, s, args);
     } else if (args.s <= 2) {
-        GL_LAUNCH((block_steps_kernel<2, false>), grid, block, 0, s, args);
+        GL_LAUNCH(block_steps_kernel<2>, grid, block, 0, s, args);
     } else if (args.s <= 4) {
-        GL_LAUNCH((block_steps_kernel<4, false>), grid, block, 0, s, args);
+        GL_LAUNCH(block_steps_kernel<4>, grid, block, 0, s, args);
     } else {
-        GL_LAUNCH((block_steps_kernel<8, false>), grid, block, 0, s, args);
+        GL_LAUNCH(block_steps_kernel<8>, grid, block, 0, s, args);
     }
 }
 

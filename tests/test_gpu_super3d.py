@@ -182,3 +182,40 @@ def test_ensemble_of_mixed_dimensions_and_regimes():
             assert np.array_equal(out[off:off + P], gpu_run(p, mem, u0, n))
         assert rel_l2(out[off:off + P], oracle.run(p, mem, u0, n)) <= TOL_PLAIN
         off += P
+
+
+def _modal(u, p, modes):
+    """Sine-mode coefficients of a 2D or 3D field at the given modes."""
+    x, y = W.coords(p["nx"]), W.coords(p["ny"])
+    if p["ndim"] == 2:
+        U = np.asarray(u).reshape(p["ny"], p["nx"])
+        return np.array([4.0 / ((p["nx"] + 1) * (p["ny"] + 1)) *
+                         (np.sin(b * np.pi * y) @ U @ np.sin(a * np.pi * x)) for a, b, _ in modes])
+    z = W.coords(p["nz"])
+    U = np.asarray(u).reshape(p["nz"], p["ny"], p["nx"])
+    return np.array([8.0 / ((p["nx"] + 1) * (p["ny"] + 1) * (p["nz"] + 1)) *
+                     np.einsum("k,j,i,kji->", np.sin(c * np.pi * z), np.sin(b * np.pi * y),
+                               np.sin(a * np.pi * x), U) for a, b, c in modes])
+
+
+@pytest.mark.parametrize("which", ["superdiffusion_2d", "diffusion_3d"])
+def test_full_size_blocked_modal_parity(which):
+    # 2D 256^2 at gamma 1.5 and 3D 64^3, 20000 steps each, in the launch configuration the
+    # benchmark times: sine-mode coefficients of the final field against the oracle's mode
+    # recursion, relative to the largest initial coefficient (the scale of the history terms)
+    w = getattr(W, which)()
+    p, n = w["problem"], w["nsteps"]
+    print_case(w["name"], "toeplitz full size")
+    got = gpu_run(p, w["memory"], w["u0"], n, sum_path="toeplitz")
+    modes = ([(1, 1, 1), (1, 3, 1), (3, 1, 1), (3, 3, 1), (2, 2, 1), (5, 5, 1)] if p["ndim"] == 2
+             else [(1, 1, 1), (1, 1, 3), (3, 1, 1), (1, 3, 3), (3, 3, 3), (2, 2, 2)])
+    c0 = _modal(w["u0"], p, modes)
+    ref = np.array([c0[i] * oracle.mode_run(p, w["memory"], a, b, 1.0, n, s=c)[-1]
+                    for i, (a, b, c) in enumerate(modes)])
+    assert np.abs(_modal(got, p, modes) - ref).max() <= TOL_MFMA * np.abs(c0).max()
+    # and over a 520-step prefix (two block boundaries) both paths match the oracle's field
+    m = 520
+    U = oracle.run(p, w["memory"], w["u0"], m)
+    for path in ("gemv", "toeplitz"):
+        assert rel_l2(gpu_run(p, w["memory"], w["u0"], m, sum_path=path), U) <= \
+            (TOL_PLAIN if path == "gemv" else TOL_MFMA)
