@@ -144,9 +144,11 @@ gl_status gl_step_n(gl_ctx *ctx, int64_t n, double *uT);
  * all problems), dt and dx held fixed.  Input dL_duT = dL/du[k_end] (FP64,
  * concatenated).  Outputs dL_du0 = dL/du0 (FP64, concatenated) and dparams,
  * nprob x 3 FP64 = {dL/dalpha, dL/dgamma, dL/drate} per problem.  Uses the
- * reverse-time sum with transposed GL weights and d psi / d gamma; the
- * current state is not changed.
- * Errors: GL_ESTATE (no step taken yet), GL_EINVAL, GL_EUNSUPPORTED, GL_EHIP. */
+ * reverse-time sum with transposed GL weights and d psi / d gamma; for
+ * adaptive memory the transpose of the schedule (offset m of reverse step k
+ * weighted by its multiplicity in the schedule of forward step k + m) is
+ * built on the host at each call.  The current state is not changed.
+ * Errors: GL_ESTATE (no step taken yet), GL_EINVAL, GL_ENOMEM, GL_EHIP. */
 gl_status gl_adjoint(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *dparams);
 
 /* Releases every resource of ctx.  gl_free(NULL) is a no-op. */

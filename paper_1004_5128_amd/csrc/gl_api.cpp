@@ -40,6 +40,8 @@ struct gl_ctx {
     double *adj_G = nullptr;     // the sums with d psi / d gamma, C x max P
     double *adj_lam[2] = {nullptr, nullptr};
     double *adj_grad = nullptr;  // per step and workgroup partial dot products, 3 each
+    gl::Run *adj_runs = nullptr;  // adaptive memory: the transposed schedule's runs
+    size_t adj_runs_cap = 0;
     int64_t maxP = 0, maxld = 0;
     int B = 256;             // block length of the Toeplitz path
     int B2 = 0;              // sub-block length inside a block (0: one level)
@@ -692,11 +694,43 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
     return GL_OK;
 }
 
+// The reverse sweep's schedule over the n steps taken: the forward schedule itself for full
+// and short memory, its transpose (built on the host, copied to adj_runs) for adaptive memory.
+gl_status reverse_schedule(gl_ctx *ctx, int64_t n, gl::Schedule *tsched,
+                           const gl::Schedule **ts, const gl::Run **truns) {
+    *ts = &ctx->sched;
+    *truns = ctx->d_runs;
+    if (ctx->opt.mem_mode != GL_MEM_ADAPTIVE) return GL_OK;
+    *tsched = gl::transpose_schedule(ctx->sched, n);
+    const size_t nruns = tsched->runs.size();
+    if (nruns > ctx->adj_runs_cap) {
+        if (ctx->adj_runs) {
+            ctx->allocs.erase(std::find(ctx->allocs.begin(), ctx->allocs.end(),
+                                        (void *)ctx->adj_runs));
+            HIP_TRY(ctx, hipFree(ctx->adj_runs));
+            ctx->adj_runs = nullptr;
+            ctx->adj_runs_cap = 0;
+        }
+        gl_status st = dev_alloc(ctx, &ctx->adj_runs, nruns);
+        if (st != GL_OK) return st;
+        ctx->adj_runs_cap = nruns;
+    }
+    HIP_TRY(ctx, hipMemcpy(ctx->adj_runs, tsched->runs.data(), nruns * sizeof(gl::Run),
+                           hipMemcpyHostToDevice));
+    *ts = tsched;
+    *truns = ctx->adj_runs;
+    return GL_OK;
+}
+
 // Reverse sweep of every problem over the steps taken so far (see gl_adjoint.hip).
 gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *dparams) {
     gl_status st;
     if ((st = adjoint_alloc(ctx)) != GL_OK) return st;
     const int64_t n = ctx->k, C = ctx->C;
+    gl::Schedule tsched;
+    const gl::Schedule *ts = nullptr;
+    const gl::Run *truns = nullptr;
+    if ((st = reverse_schedule(ctx, n, &tsched, &ts, &truns)) != GL_OK) return st;
     for (size_t ip = 0; ip < ctx->probs.size(); ++ip) {
         gl::Problem &pb = ctx->probs[ip];
         const int64_t P = pb.P;
@@ -708,14 +742,14 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
             const int64_t ks = seg * C, ke = std::min(ks + C, n);
             if ((st = adjoint_recompute(ctx, pb, ks, ke)) != GL_OK) return st;
             for (int64_t k = ke - 1; k >= ks; --k) {
-                const int64_t rho = n - 1 - k;  // reverse step: the forward schedule at rho
-                const int64_t rb = ctx->sched.run_begin[rho];
-                const int nruns = (int)(ctx->sched.run_begin[rho + 1] - rb);
-                const int64_t T = ctx->sched.terms[rho];
+                const int64_t rho = n - 1 - k;  // reverse step: the reverse schedule at rho
+                const int64_t rb = ts->run_begin[rho];
+                const int nruns = (int)(ts->run_begin[rho + 1] - rb);
+                const int64_t T = ts->terms[rho];
                 const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
                 if (nsplit > 0)
-                    gl::launch_hist_gemv(ctx->adj_M, pb.ld, P, pb.psi, ctx->d_runs + rb, nruns, rho,
-                                         1, T, nsplit, false, ctx->partial, ctx->stream);
+                    gl::launch_hist_gemv(ctx->adj_M, pb.ld, P, pb.psi, truns + rb, nruns, rho, 1,
+                                         T, nsplit, false, ctx->partial, ctx->stream);
                 const int64_t i = k - ks;
                 gl::launch_adjoint_update(pb, ctx->adj_lam[cur], ctx->adj_lam[cur ^ 1],
                                           ctx->adj_M + rho * pb.ld, ctx->partial, nsplit,
@@ -834,10 +868,6 @@ gl_status gl_adjoint(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *
     if (!ctx) return fail(nullptr, GL_EINVAL, "gl_adjoint: ctx is NULL");
     if (!dL_duT || !dL_du0 || !dparams) return fail(ctx, GL_EINVAL, "gl_adjoint: NULL argument");
     if (ctx->k < 1) return fail(ctx, GL_ESTATE, "gl_adjoint: no forward step taken");
-    if (ctx->opt.mem_mode == GL_MEM_ADAPTIVE)
-        return fail(ctx, GL_EUNSUPPORTED,
-                    "gl_adjoint: the adaptive schedule's transpose is not built (full or short "
-                    "memory only)");
     gl_status st = adjoint_impl(ctx, dL_duT, dL_du0, dparams);
     for (gl::Problem &pb : ctx->probs) {  // sums and carries reused by the recomputation
         pb.old_k0 = pb.old2_k1 = -1;

@@ -53,6 +53,13 @@ struct Schedule {
 // (full, short, adaptive with its three readings).
 Schedule build_schedule(const gl_options &opt, int64_t max_steps);
 
+// The transpose of a schedule over an n-step run, for the adjoint's reverse sweep: reverse
+// step rho (forward step k = n - 1 - rho) gets the terms (m, c), m = 0..rho, where c is the
+// multiplicity of offset m in the schedule of forward step k + m, as runs in ascending m.
+// Full and short memory are their own transposes; adaptive memory is not, since the
+// sampling of a region depends on the step that reaches it.
+Schedule transpose_schedule(const Schedule &fwd, int64_t n);
+
 // Device-side state of one problem.
 struct Problem {
     gl_problem p{};

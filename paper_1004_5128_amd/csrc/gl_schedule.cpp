@@ -103,4 +103,52 @@ Schedule build_schedule(const gl_options &opt, int64_t max_steps) {
     return s;
 }
 
+Schedule transpose_schedule(const Schedule &fwd, int64_t n) {
+    // entries (m, c) per reverse step rho = n - 1 - j, j = k - m, gathered in CSR form; for a
+    // fixed j the steps k = j, j + 1, ... give ascending m, and one step has no repeated offset
+    std::vector<int64_t> count(n + 1, 0);
+    for (int64_t k = 0; k < n; ++k)
+        for (int64_t r = fwd.run_begin[k]; r < fwd.run_begin[k + 1]; ++r) {
+            const Run &run = fwd.runs[r];
+            for (int64_t t = 0; t < run.count; ++t) ++count[n - 1 - (k - (run.m0 + t * run.stride))];
+        }
+    std::vector<int64_t> start(n + 1, 0);
+    for (int64_t rho = 0; rho < n; ++rho) start[rho + 1] = start[rho] + count[rho];
+    std::vector<int32_t> ms(start[n]), cs(start[n]);
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    for (int64_t k = 0; k < n; ++k)
+        for (int64_t r = fwd.run_begin[k]; r < fwd.run_begin[k + 1]; ++r) {
+            const Run &run = fwd.runs[r];
+            for (int64_t t = 0; t < run.count; ++t) {
+                const int64_t m = run.m0 + t * run.stride, rho = n - 1 - (k - m);
+                ms[fill[rho]] = (int32_t)m;
+                cs[fill[rho]++] = run.coef;
+            }
+        }
+    // runs: equal coefficients at a constant stride
+    Schedule out;
+    out.run_begin.reserve(n + 1);
+    out.terms.reserve(n);
+    for (int64_t rho = 0; rho < n; ++rho) {
+        out.run_begin.push_back((int64_t)out.runs.size());
+        out.terms.push_back(count[rho]);
+        for (int64_t e = start[rho]; e < start[rho + 1];) {
+            Run run{ms[e], 1, 1, cs[e]};
+            int64_t f = e + 1;
+            if (f < start[rho + 1] && cs[f] == run.coef) {
+                run.stride = ms[f] - ms[e];
+                while (f < start[rho + 1] && cs[f] == run.coef &&
+                       ms[f] - ms[f - 1] == run.stride) {
+                    ++run.count;
+                    ++f;
+                }
+            }
+            out.runs.push_back(run);
+            e = f;
+        }
+    }
+    out.run_begin.push_back((int64_t)out.runs.size());
+    return out;
+}
+
 }  // namespace gl

@@ -27,12 +27,17 @@ def gpu_adjoint(p, mem, u0, n, target, sum_path="gemv", ckpt_every=0, block_B=0)
 
 CASES = [("linear", W.memory("full"), "gemv"), ("fisher", W.memory("full"), "gemv"),
          ("linear", W.memory("short", L=9), "gemv"), ("fisher", W.memory("full"), "toeplitz"),
-         ("none", W.memory("full"), "toeplitz"), ("linear", W.memory("short", L=70), "toeplitz")]
+         ("none", W.memory("full"), "toeplitz"), ("linear", W.memory("short", L=70), "toeplitz"),
+         ("linear", W.memory("adaptive", a=2), "gemv"),
+         ("fisher", W.memory("adaptive", a=3, rule="literal"), "gemv"),
+         ("none", W.memory("adaptive", a=5), "gemv")]
 
 
 @pytest.mark.parametrize("rxn,mem,path", CASES,
                          ids=["lin-full-gemv", "fisher-full-gemv", "lin-short-gemv",
-                              "fisher-full-toeplitz", "none-full-toeplitz", "lin-short-toeplitz"])
+                              "fisher-full-toeplitz", "none-full-toeplitz", "lin-short-toeplitz",
+                              "lin-adaptive2-gemv", "fisher-adaptive3-literal-gemv",
+                              "none-adaptive5-gemv"])
 def test_adjoint_matches_oracle(rxn, mem, path):
     p = W.problem(2, 14, 0.7, 1.0, 0.05, rxn=rxn, rate=0.3)
     n = 300
@@ -60,19 +65,36 @@ def test_checkpointed_equals_single_segment(path):
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
 
 
-def test_adjoint_needs_a_run_and_full_or_short_memory():
+def test_adjoint_needs_a_run():
     G = gl()
     p = W.problem(2, 8, 0.7, 1.0, 0.05)
     u0 = torch.as_tensor(W.gaussian(p, 0)).cuda()
-    with G.Solver(p, W.memory("full"), u0, max_steps=10) as s:
-        with pytest.raises(G.GLError) as e:
-            s.adjoint(u0)
-        assert e.value.status == G.GL_ESTATE
-    with G.Solver(p, W.memory("adaptive", a=2), u0, max_steps=10) as s:
-        s.step(5)
-        with pytest.raises(G.GLError) as e:
-            s.adjoint(u0)
-        assert e.value.status == G.GL_EUNSUPPORTED
+    for mem in (W.memory("full"), W.memory("adaptive", a=2)):
+        with G.Solver(p, mem, u0, max_steps=10) as s:
+            with pytest.raises(G.GLError) as e:
+                s.adjoint(u0)
+            assert e.value.status == G.GL_ESTATE
+
+
+def test_adaptive_adjoint_after_longer_runs_matches_oracle():
+    # the transposed schedule depends on the run length: gradients after 150 steps, then after
+    # continuing to 420 (a longer transpose), then after a reset and 90 steps, each against
+    # the oracle's adjoint of that run
+    p = W.problem(2, 15, 0.6, 1.0, 0.08, rxn="linear", rate=0.4)
+    mem = W.memory("adaptive", a=2)
+    u0 = 0.5 * W.gaussian(p, 7) + 0.1
+    G = gl()
+    print_case("adaptive adjoint, several lengths")
+    with G.Solver(p, mem, torch.as_tensor(u0), max_steps=420, ckpt_every=50) as s:
+        for n, fresh in ((150, False), (420, False), (90, True)):
+            if fresh:
+                s.reset(torch.as_tensor(u0))
+            uT = s.step(n - s.k)
+            target = oracle.run(dict(p, gamma=0.55), mem, u0, n)
+            du0, dpar = s.adjoint(uT - torch.as_tensor(target).cuda())
+            Lr, du0r, dparr = oracle.adjoint(p, mem, u0, n, target)
+            assert rel_l2(du0.cpu().numpy(), du0r) <= 1e-7, n
+            assert np.all(np.abs(dpar[0].cpu().numpy() - dparr) <= 1e-7 * np.abs(dparr)), n
 
 
 def _loss(p, mem, u0, n, target, path):

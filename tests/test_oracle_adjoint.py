@@ -14,24 +14,28 @@ def loss(p, mem, u0, n, target):
 
 
 CASES = [
-    (2, "linear", W.memory("full")),
-    (2, "fisher", W.memory("full")),
-    (1, "linear", W.memory("short", L=6)),
-    (2, "linear", W.memory("adaptive", a=2)),
-    (2, "fisher", W.memory("adaptive", a=3, rule="literal")),
+    (2, "linear", W.memory("full"), 0.7),
+    (2, "fisher", W.memory("full"), 0.7),
+    (1, "linear", W.memory("short", L=6), 0.7),
+    (2, "linear", W.memory("adaptive", a=2), 0.7),
+    (2, "fisher", W.memory("adaptive", a=3, rule="literal"), 0.7),
+    (3, "fisher", W.memory("full"), 0.7),
+    (2, "linear", W.memory("full"), 1.5),
+    (1, "linear", W.memory("adaptive", a=2), 2.0),
 ]
 
 
-@pytest.mark.parametrize("ndim,rxn,mem", CASES,
+@pytest.mark.parametrize("ndim,rxn,mem,gamma", CASES,
                          ids=lambda c: str(c) if not isinstance(c, dict) else c["mode"] + c["rule"])
-def test_adjoint_matches_central_differences(ndim, rxn, mem):
-    p = W.problem(ndim, 7, 0.7, 1.0, 0.05, rxn=rxn, rate=0.3)
+def test_adjoint_matches_central_differences(ndim, rxn, mem, gamma):
+    p = W.problem(ndim, 7, gamma, 1.0, 0.05, rxn=rxn, rate=0.3)
     n = 60
     u0 = W.gaussian(p, 4) * 0.5 + 0.1
-    tp = dict(p, gamma=0.65, alpha=1.2)
+    tp = dict(p, gamma=gamma - 0.05, alpha=1.2)
     target = oracle.run(tp, mem, u0, n)
     L, du0, dpar = oracle.adjoint(p, mem, u0, n, target)
-    assert abs(L - loss(p, mem, u0, n, target)) <= 1e-15 * L
+    # the same P squared errors summed in two orders (sequential in C, pairwise in numpy)
+    assert abs(L - loss(p, mem, u0, n, target)) <= 1e-13 * L
 
     for idx, key in enumerate(("alpha", "gamma", "rate")):
         h = 1e-5 * p[key]
