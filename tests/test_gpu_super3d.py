@@ -219,3 +219,27 @@ def test_full_size_blocked_modal_parity(which):
     for path in ("gemv", "toeplitz"):
         assert rel_l2(gpu_run(p, w["memory"], w["u0"], m, sum_path=path), U) <= \
             (TOL_PLAIN if path == "gemv" else TOL_MFMA)
+
+
+def test_blocked_path_with_mixed_dimensions():
+    # one blocked-path context over a 3D, a 2D superdiffusive and a 1D problem: the 3D member
+    # holds the context to two in-block steps per launch; every member matches its solo run
+    # bit for bit (the in-block chain does not depend on the grouping) and the oracle
+    probs = [box((10, 9, 7), 0.7, 0.05, rxn="fisher", rate=0.5),
+             W.problem(2, 23, 1.4, 1.0, 0.15, rxn="linear", rate=0.2),
+             W.problem(1, 300, 0.5, 1.0, 0.2)]
+    u0s = [W.uniform_field(probs[0], 40), W.gaussian(probs[1], 41), W.sine_mode(probs[2], 2)]
+    mem = W.memory("full")
+    n = 600
+    print_case("blocked mixed dimensions", n)
+    G = gl()
+    with G.Solver(probs, mem, torch.as_tensor(np.concatenate(u0s)), max_steps=n,
+                  sum_path="toeplitz", block_B=128) as s:
+        out = s.step(n).cpu().numpy()
+    off = 0
+    for p, u0 in zip(probs, u0s):
+        P = W.npoints(p)
+        assert np.array_equal(out[off:off + P], gpu_run(p, mem, u0, n, sum_path="toeplitz",
+                                                        block_B=128))
+        assert rel_l2(out[off:off + P], oracle.run(p, mem, u0, n)) <= TOL_MFMA
+        off += P
