@@ -31,7 +31,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, GB/s
 BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix, TFLOP/s
-PREFIX_STEPS = 1200           # oracle sample: the first 800 steps of the workload
+PREFIX_MACS = 4.72e10   # oracle sample: the first steps of the workload, about this many MACs
+
+
+def grid_of(p):
+    return [p["nx"], p["ny"]] + ([p["nz"]] if p["ndim"] == 3 else [])
+
+
+def prefix_steps(P):
+    """Steps of the oracle's prefix run for P points: 1200 at 256^2, 600 at 64^3."""
+    return max(100, int(round(np.sqrt(2 * PREFIX_MACS / P) / 100)) * 100)
+
+
+WORKLOADS = ("2d_256", "superdiffusion_2d", "diffusion_3d")
+WORKLOAD_NAMES = {
+    "2d_256": "2d_256x256_gamma0.8_alpha1_linear0.1_gaussian_r0.1_20000steps_full",
+    "superdiffusion_2d": "2d_256x256_gamma1.5_alpha1_none_gaussian_r0.1_20000steps_full",
+    "diffusion_3d": "3d_64x64x64_gamma0.8_alpha1_linear0.1_gaussian_r0.05_20000steps_full"}
 MODES = [(1, 1), (1, 3), (3, 1), (3, 3), (1, 5), (5, 5)]
 
 
@@ -260,6 +276,8 @@ def algorithmic_work(path, P, n, B, terms, ndim=2):
 
 
 def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
+    """One history-sum path on workload w: `steps` timed solves after `warmup`, one solve
+    with per-kernel events, and (prefix) the state after the oracle's prefix length."""
     import torch
     from paper_1004_5128_amd import gl
     p = w["problem"]
@@ -296,7 +314,7 @@ def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
     u_prefix = None
     if prefix:   # prefix run for the oracle comparison
         s.reset(u0)
-        s.advance(PREFIX_STEPS)
+        s.advance(prefix_steps(P))
         u_prefix = s.state().cpu().numpy()
     s.close()
     ms = (t1 - t0) * 1e3 / steps
@@ -444,7 +462,7 @@ def run_extra_workloads(block_B, with_oracle):
         r = run_path("toeplitz", w, 1, 1, block_B, prefix=False)
         d = {"ms_per_solve": r["ms_per_step"], "history_macs_per_solve": r["macs"],
              "value": r["macs"] / (r["ms_per_step"] / 1e3), "unit": "history MACs/s",
-             "grid": [p["nx"], p["ny"]] + ([p["nz"]] if p["ndim"] == 3 else []),
+             "grid": grid_of(p),
              "gamma": p["gamma"], "time_steps": n}
         kern = {}
         for name, (cnt, ms) in r["prof"].items():
@@ -501,6 +519,9 @@ def main():
                     help="skip the short / adaptive memory runs of the same workload")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the superdiffusion and 3D workloads")
+    ap.add_argument("--workload", choices=WORKLOADS, default="2d_256",
+                    help="the headline workload (default: 2D 256^2, gamma 0.8); the others run "
+                         "without the memory-mode and extra-workload legs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a 1 GiB device copy (reference for traffic counters)")
     ap.add_argument("--profile-steps", type=int, default=0,
@@ -547,9 +568,14 @@ def main():
     import torch
     from paper_1004_5128_amd import workloads as W
     torch.cuda.set_device(0)
-    w = W.cfg2()
+    w = {"2d_256": W.cfg2, "superdiffusion_2d": W.superdiffusion_2d,
+         "diffusion_3d": W.diffusion_3d}[args.workload]()
     p, n = w["problem"], w["nsteps"]
     P = W.npoints(p)
+    modes = MODES3 if p["ndim"] == 3 else MODES
+    if args.workload != "2d_256":
+        args.no_modes = args.no_extra = True
+    n_pre = prefix_steps(P)
 
     if args.copy_calibration:
         copy_calibration()
@@ -567,18 +593,20 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        log("oracle prefix", PREFIX_STEPS, "steps on", oracle.num_threads(), "threads")
+        log("oracle prefix", n_pre, "steps on", oracle.num_threads(), "threads")
         t0 = time.perf_counter()
-        oracle_prefix = oracle.run(p, w["memory"], w["u0"], PREFIX_STEPS)
+        oracle_prefix = oracle.run(p, w["memory"], w["u0"], n_pre)
         t_cpu = time.perf_counter() - t0
-        macs_cpu = P * PREFIX_STEPS * (PREFIX_STEPS + 1) // 2
+        macs_cpu = P * n_pre * (n_pre + 1) // 2
         cpu = {"value": macs_cpu / t_cpu, "unit": "history MACs/s", "cores": oracle.num_threads(),
                "kind": "oracle",
-               "sample": "first %d of the %d steps of the same 256x256 workload (%.3g MACs, "
-                         "%.1f s)" % (PREFIX_STEPS, n, macs_cpu, t_cpu)}
-        c0 = modal(w["u0"], p, MODES)
-        oracle_modal = np.array([c0[i] * oracle.mode_run(p, w["memory"], a, b, 1.0, n)[-1]
-                                 for i, (a, b) in enumerate(MODES)])
+               "sample": "first %d of the %d steps of the same %s workload (%.3g MACs, "
+                         "%.1f s)" % (n_pre, n, "x".join(str(v) for v in grid_of(p)), macs_cpu,
+                                      t_cpu)}
+        c0 = modal(w["u0"], p, modes)
+        oracle_modal = np.array([c0[i] * oracle.mode_run(p, w["memory"], m[0], m[1], 1.0, n,
+                                                         s=m[2] if len(m) > 2 else 1)[-1]
+                                 for i, m in enumerate(modes)])
 
     for path, r in res.items():
         d = {"ms_per_step": r["ms_per_step"], "value": r["macs"] / (r["ms_per_step"] / 1e3)}
@@ -601,7 +629,7 @@ def main():
         if oracle_prefix is not None:
             d["rel_l2_vs_oracle_prefix"] = float(np.linalg.norm(r["u_prefix"] - oracle_prefix) /
                                                  np.linalg.norm(oracle_prefix))
-            cg = modal(r["uT"], p, MODES)
+            cg = modal(r["uT"], p, modes)
             d["modal_err_vs_oracle_full_length"] = float(np.abs(cg - oracle_modal).max() /
                                                          np.abs(oracle_modal).max())
         out_paths[path] = d
@@ -634,8 +662,8 @@ def main():
         "scaling": "weak", "vs_baseline": None,
         "dtype": "bf16x3 mfma (f32 acc) + f64" if primary == "toeplitz" else "f32 history, f64 accumulate",
         "data": "synthetic",
-        "config": {"workload": "2d_256x256_gamma0.8_alpha1_linear0.1_gaussian_r0.1_20000steps_full",
-                   "grid": [p["nx"], p["ny"]], "time_steps": args.profile_steps or n,
+        "config": {"workload": WORKLOAD_NAMES[args.workload],
+                   "grid": grid_of(p), "time_steps": args.profile_steps or n,
                    "memory": "full",
                    "history_macs_per_solve": r["macs"], "path": primary},
         "paths": out_paths,
