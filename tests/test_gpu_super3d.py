@@ -243,3 +243,27 @@ def test_blocked_path_with_mixed_dimensions():
                                                         block_B=128))
         assert rel_l2(out[off:off + P], oracle.run(p, mem, u0, n)) <= TOL_MFMA
         off += P
+
+
+def test_blocked_path_error_paths():
+    # capacity, and a blow-up through the reaction term on a 3D grid, on the blocked path
+    G = gl()
+    p = box((9, 8, 7), 0.8, 0.05)
+    u0 = torch.as_tensor(W.gaussian(p, 42)).cuda()
+    print_case("blocked errors")
+    with G.Solver(p, W.memory("full"), u0, max_steps=300, sum_path="toeplitz", block_B=64) as s:
+        s.step(0)
+        s.step(299)
+        with pytest.raises(G.GLError) as e:
+            s.step(2)
+        assert e.value.status == G.GL_ECAPACITY
+        assert s.k == 299
+        s.step(1)
+        assert s.k == 300
+    q = W.problem(3, 6, 0.9, 1e-6, None, rxn="linear", rate=-1e300, dt=1e-3)
+    q.update(ny=5, nz=4)
+    with G.Solver(q, W.memory("full"), torch.ones(120, dtype=torch.float64).cuda(), max_steps=40,
+                  sum_path="toeplitz", block_B=32, check_finite=True) as s:
+        with pytest.raises(G.GLError) as e:
+            s.step(40)
+        assert e.value.status == G.GL_ENONFINITE
