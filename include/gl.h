@@ -164,6 +164,26 @@ const char *gl_last_error(const gl_ctx *ctx);
  * Errors: GL_EINVAL, GL_ENONFINITE (u0 not finite), GL_EHIP. */
 gl_status gl_reset(gl_ctx *ctx, const double *u0);
 
+/* Launch-shape autotuning of a context (no paper passage: a property of the GPU, not of
+ * the method).  At step 0 (after gl_init or gl_reset), times candidate launch shapes of the
+ * history sums on this context's own problems at step max_steps / 2, the mean depth of a
+ * full-memory run, and keeps the fastest:
+ *   GL_TUNE_GEMV     the plain path's GEMV workgroup target (its split-K fan-out;
+ *                    candidates 256 .. 4096, default 1024), one GEMV + update step each;
+ *   GL_TUNE_PRODUCT  the blocked path's product workgroups per CU (its chunk count;
+ *                    candidates 1, 2, 4, default 2), one block product each (skipped when
+ *                    GL_TOEPLITZ_KCHUNK fixes the chunk length, or max_steps / 2 < block_B).
+ * what = 0 tunes both.  The candidates read the history arena as it stands and write only
+ * rows, states and sums that the run overwrites before reading, so the context stays at
+ * step 0 with its initial fields.  The chosen shapes change the order of floating-point
+ * sums (split and chunk boundaries), not the operation; results stay within the paths'
+ * tolerances.  If chosen is not NULL (host, 2 entries) it receives the GEMV target and the
+ * product's workgroups per CU in effect (0: fixed chunk length).
+ * Errors: GL_EINVAL (NULL ctx, unknown bits in what), GL_ESTATE (steps taken), GL_EHIP. */
+#define GL_TUNE_GEMV 1
+#define GL_TUNE_PRODUCT 2
+gl_status gl_autotune(gl_ctx *ctx, int32_t what, int64_t *chosen);
+
 /* ---- inspection and component entry points (tests and benchmarks) ---- */
 
 /* Kernels timed by the profiling mode. */

@@ -31,6 +31,7 @@ struct gl_ctx {
     gl::BatchEntry *d_batch = nullptr;  // one entry per problem (batched plain-path launches)
 
     double *bpartial = nullptr;          // per-problem GEMV partial regions of the batch
+    size_t bpart_cap = 0;                // its length in doubles
     int64_t upd_wgs = 0;                 // workgroups of one batched update launch
     int64_t C = 500;         // adjoint recompute segment length (snapshot interval)
     // adjoint work buffers, allocated on the first gl_adjoint call (sized for the largest problem)
@@ -180,28 +181,74 @@ const char *env_value(const char *name) {
 
 // History rows per chunk of a Toeplitz product over `rows` rows (a multiple of the K step):
 // the fixed GL_TOEPLITZ_KCHUNK length if set, else the fewest chunks for which the column
-// tiles x chunks fill the GPU (two workgroups per CU, one for the 512-row block).  Fewer
-// chunks mean fewer FP32 partial products to write and sum; the accumulation error is set by
-// the BF16 split, not by the FP32 sums over a chunk.
-int64_t chunk_cap(const gl_ctx *ctx, int BM, int64_t P, int64_t rows) {
+// tiles x chunks reach `wgs` workgroups per CU (half as many for the 512-row block; 2 by
+// default, gl_autotune may pick another).  Fewer chunks mean fewer FP32 partial products to
+// write and sum; the accumulation error is set by the BF16 split, not by the FP32 sums over
+// a chunk.
+int64_t chunk_cap(const gl_ctx *ctx, int BM, int64_t P, int64_t rows, int64_t wgs) {
     const int64_t tiles = (P + 127) / 128;
-    const int64_t target = (int64_t)std::max(ctx->ncu, 1) * (BM >= 512 ? 1 : 2);
+    const int64_t target =
+        (int64_t)std::max(ctx->ncu, 1) * (BM >= 512 ? std::max<int64_t>(1, wgs / 2) : wgs);
     const int64_t nchunk = std::max<int64_t>(1, (target + tiles - 1) / tiles);
     return std::max<int64_t>(1, std::min(nchunk, (rows + gl::kMaxTK - 1) / gl::kMaxTK));
 }
 
 int64_t chunk_rows(const gl_ctx *ctx, int BM, int64_t P, int64_t rows) {
     if (ctx->tune.kchunk > 0) return ctx->tune.kchunk;
-    const int64_t kc = (std::max<int64_t>(rows, 1) + chunk_cap(ctx, BM, P, rows) - 1) /
-                       chunk_cap(ctx, BM, P, rows);
+    const int64_t cap = chunk_cap(ctx, BM, P, rows, ctx->tune.chunk_wgs);
+    const int64_t kc = (std::max<int64_t>(rows, 1) + cap - 1) / cap;
     return (kc + gl::kMaxTK - 1) / gl::kMaxTK * gl::kMaxTK;
 }
 
-// Most chunks any product over at most `rows` rows is cut into (sizes the chunk buffer):
-// rows / chunk_rows <= chunk_cap, which does not decrease with rows.
+// Most chunks any product over at most `rows` rows is cut into, for any workgroup target
+// gl_autotune may choose (sizes the chunk buffer): rows / chunk_rows <= chunk_cap, which
+// does not decrease with rows or with the target.
 int64_t max_chunks(const gl_ctx *ctx, int BM, int64_t P, int64_t rows) {
     if (ctx->tune.kchunk > 0) return gl::toeplitz_chunks(rows, ctx->tune.kchunk);
-    return chunk_cap(ctx, BM, P, rows);
+    return chunk_cap(ctx, BM, P, rows, gl::kMaxChunkWgs);
+}
+
+// The GEMV workgroup target of every problem (an ensemble shares `groups` in proportion to
+// the problems' sizes), each problem's region of batched partial sums (its largest split
+// count over the schedule) and the device table of the batched launches.  The stream must
+// be idle: the table is rewritten in place.
+gl_status apply_gemv_target(gl_ctx *ctx, int64_t groups) {
+    ctx->tune.gemv_groups = groups;
+    int64_t max_terms = 1;
+    for (int64_t t : ctx->sched.terms) max_terms = std::max(max_terms, t);
+    const int32_t nprob = (int32_t)ctx->probs.size();
+    std::vector<gl::BatchEntry> tab(nprob);
+    size_t off = 0;
+    for (int32_t i = 0; i < nprob; ++i) {
+        gl::Problem &pb = ctx->probs[i];
+        pb.gemv_groups = std::max<int64_t>(
+            1, (groups * pb.P + ctx->total_points - 1) / ctx->total_points);
+        const int splits = std::max(1, gl::gemv_splits(max_terms - 1, pb.P, pb.gemv_groups));
+        gl::BatchEntry &e = tab[i];
+        e.H = pb.H;
+        e.ld = pb.ld;
+        e.P = pb.P;
+        e.psi = pb.psi;
+        e.u[0] = pb.u[0];
+        e.u[1] = pb.u[1];
+        e.partial = ctx->bpartial + off;
+        e.snap = pb.snap;
+        e.groups = pb.gemv_groups;
+        off += (size_t)splits * pb.P;
+        e.ndim = pb.p.ndim;
+        e.nx = pb.p.nx;
+        e.ny = pb.p.ny;
+        e.nz = pb.p.nz;
+        e.rxn = pb.p.rxn;
+        e.r = pb.r;
+        e.dt = pb.p.dt;
+        e.rate = pb.p.rxn_rate;
+    }
+    if (off > ctx->bpart_cap)
+        return fail(ctx, GL_EINVAL, "internal: batched partial sums exceed their buffer");
+    HIP_TRY(ctx, hipMemcpy(ctx->d_batch, tab.data(), tab.size() * sizeof(gl::BatchEntry),
+                           hipMemcpyHostToDevice));
+    return GL_OK;
 }
 
 gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const double *u0) {
@@ -265,20 +312,10 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
                     need / 1e9, free_b / 1e9);
 
     ctx->sched = gl::build_schedule(opt, opt.max_steps);
-    int64_t max_terms = 1;
-    for (int64_t t : ctx->sched.terms) max_terms = std::max(max_terms, t);
-    std::vector<int64_t> bsplits(nprob);
-    size_t bpart = 0;
-    for (int32_t i = 0; i < nprob; ++i) {
-        gl::Problem &pb = ctx->probs[i];
-        // an ensemble shares the workgroup target in proportion to the problems' sizes
-        pb.gemv_groups = std::max<int64_t>(
-            1, (ctx->tune.gemv_groups * pb.P + ctx->total_points - 1) / ctx->total_points);
-        bsplits[i] = std::max(1, gl::gemv_splits(max_terms - 1, pb.P, pb.gemv_groups));
-        bpart += (size_t)bsplits[i] * pb.P;
-    }
     gl_status st;
-    if ((st = dev_alloc(ctx, &ctx->bpartial, bpart))) return st;
+    // room for every problem's largest split count, whatever GEMV target gl_autotune picks
+    ctx->bpart_cap = (size_t)gl::kMaxSplits * ctx->total_points;
+    if ((st = dev_alloc(ctx, &ctx->bpartial, ctx->bpart_cap))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_batch, (size_t)nprob))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_runs, ctx->sched.runs.size()))) return st;
     HIP_TRY(ctx, hipMemcpy(ctx->d_runs, ctx->sched.runs.data(),
@@ -325,33 +362,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
             HIP_TRY(ctx, hipGetLastError());
         }
     }
-    // device table of the problems for the batched launches
-    std::vector<gl::BatchEntry> tab(nprob);
-    size_t off = 0;
-    for (int32_t i = 0; i < nprob; ++i) {
-        const gl::Problem &pb = ctx->probs[i];
-        gl::BatchEntry &e = tab[i];
-        e.H = pb.H;
-        e.ld = pb.ld;
-        e.P = pb.P;
-        e.psi = pb.psi;
-        e.u[0] = pb.u[0];
-        e.u[1] = pb.u[1];
-        e.partial = ctx->bpartial + off;
-        e.snap = pb.snap;
-        e.groups = pb.gemv_groups;
-        off += (size_t)bsplits[i] * pb.P;
-        e.ndim = pb.p.ndim;
-        e.nx = pb.p.nx;
-        e.ny = pb.p.ny;
-        e.nz = pb.p.nz;
-        e.rxn = pb.p.rxn;
-        e.r = pb.r;
-        e.dt = pb.p.dt;
-        e.rate = pb.p.rxn_rate;
-    }
-    HIP_TRY(ctx, hipMemcpy(ctx->d_batch, tab.data(), tab.size() * sizeof(gl::BatchEntry),
-                           hipMemcpyHostToDevice));
+    if ((st = apply_gemv_target(ctx, ctx->tune.gemv_groups)) != GL_OK) return st;
     return load_initial(ctx, u0);
 }
 
@@ -776,6 +787,116 @@ gl_status copy_state(gl_ctx *ctx, double *dst) {
     return GL_OK;
 }
 
+// Fastest of `reps` timed runs of launch() on the context's stream after one untimed run, in
+// milliseconds, from events recorded around it.
+template <class F>
+gl_status time_best(gl_ctx *ctx, int reps, F launch, float *best) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, GL_EHIP, "hipEventCreate failed");
+    }
+    gl_status st = GL_OK;
+    *best = 0.f;
+    for (int r = 0; r <= reps && st == GL_OK; ++r) {
+        if ((st = launch()) != GL_OK) break;  // r = 0: the untimed run
+        if (r == 0) continue;
+        float ms = 0.f;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess || (st = launch()) != GL_OK ||
+            hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            if (st == GL_OK) st = fail(ctx, GL_EHIP, "timing a candidate failed");
+            break;
+        }
+        if (r == 1 || ms < *best) *best = ms;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+// Candidate launch shapes timed on the context's own problems at step max_steps / 2 (the
+// mean depth of a full-memory run), keeping the fastest:
+//  - plain path: the GEMV workgroup target (split-K fan-out), one GEMV + update step of
+//    every problem per candidate;
+//  - blocked path: the product's workgroups per CU (its chunk count), the block product of
+//    every problem over the rows before the block at that depth.
+// Kernels read the history arena as it stands and write only rows, states and sums that
+// the run overwrites before reading them, so the context stays at step 0.
+gl_status autotune_impl(gl_ctx *ctx, int32_t what, int64_t *chosen) {
+    const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
+    const int64_t kmid = std::max<int64_t>(1, ctx->opt.max_steps / 2);
+    const int nprob = (int)ctx->probs.size();
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    const bool prof = ctx->prof;
+    ctx->prof = false;  // no per-kernel events around the candidates
+    gl_status st = GL_OK;
+    if ((what & GL_TUNE_GEMV) && st == GL_OK) {
+        const int64_t rb = ctx->sched.run_begin[kmid];
+        const int nruns = (int)(ctx->sched.run_begin[kmid + 1] - rb);
+        const int64_t T = ctx->sched.terms[kmid];
+        const int cur = ctx->probs[0].cur;
+        float best = 0.f;
+        int64_t best_g = ctx->tune.gemv_groups;
+        for (int64_t g : {256, 512, 1024, 2048, 4096}) {
+            HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+            if ((st = apply_gemv_target(ctx, g)) != GL_OK) break;
+            float ms = 0.f;
+            st = time_best(ctx, 3, [&]() -> gl_status {
+                const int64_t wgs = gl::batched_gemv_groups(ctx->probs, T - 1);
+                if (wgs > 0)
+                    gl::launch_hist_gemv_batched(ctx->d_batch, nprob, wgs, ctx->d_runs + rb,
+                                                 nruns, kmid, 1, T, false, ctx->stream);
+                gl::launch_update_batched(ctx->d_batch, nprob, ctx->upd_wgs, kmid, cur, T - 1,
+                                          ctx->C, ctx->stream);
+                HIP_TRY(ctx, hipGetLastError());
+                return GL_OK;
+            }, &ms);
+            if (st != GL_OK) break;
+            if (g == 256 || ms < best) {
+                best = ms;
+                best_g = g;
+            }
+        }
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+        if (st == GL_OK) st = apply_gemv_target(ctx, best_g);
+    }
+    const int64_t k0 = kmid / ctx->B * ctx->B;
+    if ((what & GL_TUNE_PRODUCT) && toep && ctx->tune.kchunk == 0 && k0 >= ctx->B && st == GL_OK) {
+        float best = 0.f;
+        int64_t best_w = ctx->tune.chunk_wgs;
+        for (int64_t w = 1; w <= gl::kMaxChunkWgs && st == GL_OK; w *= 2) {
+            ctx->tune.chunk_wgs = w;
+            float ms = 0.f;
+            st = time_best(ctx, 2, [&]() -> gl_status {
+                for (gl::Problem &pb : ctx->probs) {
+                    gl_status s2 = block_old(ctx, pb, pb.H, pb.ld, k0, pb.old);
+                    if (s2 != GL_OK) return s2;
+                }
+                HIP_TRY(ctx, hipGetLastError());
+                return GL_OK;
+            }, &ms);
+            if (st == GL_OK && (w == 1 || ms < best)) {
+                best = ms;
+                best_w = w;
+            }
+        }
+        ctx->tune.chunk_wgs = best_w;
+        for (gl::Problem &pb : ctx->probs) {  // the sums written here are not the run's
+            pb.old_k0 = pb.old2_k1 = -1;
+            pb.carry_k = -1;
+        }
+    }
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    ctx->prof = prof;
+    if (st == GL_OK && chosen) {
+        chosen[0] = ctx->tune.gemv_groups;
+        chosen[1] = ctx->tune.kchunk > 0 ? 0 : ctx->tune.chunk_wgs;
+    }
+    return st;
+}
+
 }  // namespace
 
 extern "C" {
@@ -840,6 +961,16 @@ gl_status gl_reset(gl_ctx *ctx, const double *u0) {
     if (!ctx) return fail(nullptr, GL_EINVAL, "gl_reset: ctx is NULL");
     if (!u0) return fail(ctx, GL_EINVAL, "gl_reset: u0 is NULL");
     return load_initial(ctx, u0);
+}
+
+gl_status gl_autotune(gl_ctx *ctx, int32_t what, int64_t *chosen) {
+    if (!ctx) return fail(nullptr, GL_EINVAL, "gl_autotune: ctx is NULL");
+    if (what & ~(GL_TUNE_GEMV | GL_TUNE_PRODUCT))
+        return fail(ctx, GL_EINVAL, "gl_autotune: unknown bits in what = %d", what);
+    if (ctx->k != 0)
+        return fail(ctx, GL_ESTATE, "gl_autotune: %lld steps taken (tune at step 0)",
+                    (long long)ctx->k);
+    return autotune_impl(ctx, what ? what : GL_TUNE_GEMV | GL_TUNE_PRODUCT, chosen);
 }
 
 gl_status gl_set_profiling(gl_ctx *ctx, int32_t on) {

@@ -146,7 +146,10 @@ struct Tuning {
                                  // 0: per product, the fewest chunks that fill the GPU
     int64_t sub_B = 32;          // sub-block length of the blocked path (32 or 64; 0: off)
     int64_t fuse = 8;            // in-block steps per launch (1 .. kMaxFuse; kMaxFuse3 in 3D)
+    int64_t chunk_wgs = 2;       // product workgroups per CU that the column tiles x chunks
+                                 // should reach (half of it for 512-row blocks); 1 .. kMaxChunkWgs
 };
+constexpr int64_t kMaxChunkWgs = 4;
 
 // ---- blocked Toeplitz path
 constexpr int kPsiPad = 128;  // zero entries before psi(0) in the BF16 weight tables

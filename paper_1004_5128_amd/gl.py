@@ -26,6 +26,8 @@ GL_ESTATE = -5
 GL_ENONFINITE = -6
 GL_EHIP = -7
 GL_EUNSUPPORTED = -8
+GL_TUNE_GEMV = 1
+GL_TUNE_PRODUCT = 2
 
 GL_RXN = {"none": 0, "linear": 1, "fisher": 2}
 GL_MEM = {"full": 0, "short": 1, "adaptive": 2}
@@ -51,8 +53,8 @@ class gl_options(C.Structure):
 
 
 EXPORTS = ["gl_init", "gl_step_n", "gl_adjoint", "gl_free", "gl_last_error", "gl_reset",
-           "gl_set_profiling", "gl_profile", "gl_steps_done", "gl_get_state", "gl_get_weights",
-           "gl_schedule_terms", "gl_history_sum"]
+           "gl_autotune", "gl_set_profiling", "gl_profile", "gl_steps_done", "gl_get_state",
+           "gl_get_weights", "gl_schedule_terms", "gl_history_sum"]
 
 GL_KERNEL_HIST_GEMV = 0
 GL_KERNEL_UPDATE = 1
@@ -78,6 +80,7 @@ def _load():
         "gl_free": (None, [ctxp]),
         "gl_last_error": (C.c_char_p, [ctxp]),
         "gl_reset": (i32, [ctxp, vp]),
+        "gl_autotune": (i32, [ctxp, i32, C.POINTER(i64)]),
         "gl_set_profiling": (i32, [ctxp, i32]),
         "gl_profile": (i32, [ctxp, i32, C.POINTER(i64), C.POINTER(C.c_double)]),
         "gl_steps_done": (i64, [ctxp]),
@@ -142,6 +145,14 @@ def gl_last_error(ctx=None):
 
 def gl_reset(ctx, u0):
     _check(_lib.gl_reset(ctx, _ptr(u0)), ctx)
+
+
+def gl_autotune(ctx, what=0):
+    """Times candidate launch shapes at step 0 and keeps the fastest; returns (GEMV workgroup
+    target, product workgroups per CU)."""
+    chosen = (C.c_int64 * 2)()
+    _check(_lib.gl_autotune(ctx, int(what), chosen), ctx)
+    return int(chosen[0]), int(chosen[1])
 
 
 def gl_set_profiling(ctx, on):
@@ -256,6 +267,9 @@ class Solver:
     def reset(self, u0):
         u0 = torch.as_tensor(u0).to(device=self.device, dtype=torch.float64).contiguous().reshape(-1)
         gl_reset(self.ctx, u0)
+
+    def autotune(self, what=0):
+        return gl_autotune(self.ctx, what)
 
     def set_profiling(self, on):
         gl_set_profiling(self.ctx, on)

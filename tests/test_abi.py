@@ -122,6 +122,12 @@ def test_validation_errors(lib, prob_kw, opt_kw, code):
     assert msg and ctx.value is None
 
 
+def test_autotune_rejects_null_context(lib):
+    lib.gl_autotune.restype = C.c_int32
+    lib.gl_autotune.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+    assert lib.gl_autotune(None, 0, None) == -1
+
+
 def test_nprob_zero_and_free_null(lib):
     st, msg, _ = _init(lib, {}, {}, nprob=0)
     assert st == -1 and "nprob" in msg
