@@ -448,6 +448,50 @@ def paper_fig3(reps=2):
           flush=True)
 
 
+def run_adjoint_leg():
+    """The adjoint workload (2D 128^2, gamma 0.7, alpha 1, f = -0.2 u, 5000 steps, checkpoints
+    every 500 steps; target: the same run at gamma 0.65, alpha 1.2) on both paths: forward
+    and gl_adjoint times (one warmup each), and the directional derivative <dL/du0, v>
+    against a central difference of the GPU loss (exact for a quadratic loss of a linear
+    scheme, step 0.1)."""
+    import torch
+    from paper_1004_5128_amd import gl, workloads as W
+    w = W.cfg4()
+    p, mem, n = w["problem"], w["memory"], w["nsteps"]
+    u0 = torch.as_tensor(w["u0"]).cuda()
+    v = torch.as_tensor(w["direction"]).cuda()
+    out = {}
+    for path in ("gemv", "toeplitz"):
+        log("adjoint", path)
+        with gl.Solver(w["target_problem"], mem, u0, max_steps=n, sum_path=path) as s:
+            target = s.step(n).clone()
+
+        def loss(x):
+            with gl.Solver(p, mem, x, max_steps=n, sum_path=path) as s2:
+                return 0.5 * float(torch.sum((s2.step(n) - target) ** 2))
+
+        with gl.Solver(p, mem, u0, max_steps=n, sum_path=path,
+                       ckpt_every=w["ckpt_every"]) as s:
+            times = []
+            for _ in range(2):   # the first of each is the warmup
+                s.reset(u0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                uT = s.step(n)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                du0, dpar = s.adjoint(uT - target)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                times.append((t1 - t0, t2 - t1))
+        fd = (loss(u0 + 0.1 * v) - loss(u0 - 0.1 * v)) / 0.2
+        out[path] = {"forward_ms": times[-1][0] * 1e3, "adjoint_ms": times[-1][1] * 1e3,
+                     "adjoint_over_forward": times[-1][1] / times[-1][0],
+                     "directional_derivative_rel_err_vs_fd":
+                         abs(float(du0 @ v) - fd) / abs(fd)}
+    return out
+
+
 def run_extra_workloads(block_B, with_oracle):
     """Superdiffusion (2D 256^2, gamma 1.5) and a 3D grid (64^3, 7-point stencil), 20000 steps
     each, full memory, on the blocked path: time per solve (one warmup, one timed), history
@@ -644,6 +688,7 @@ def main():
 
     if not args.no_extra and not args.profile_steps:
         out_paths["workloads"] = run_extra_workloads(args.block_B, not args.no_cpu)
+        out_paths["adjoint_128x128_5000steps"] = run_adjoint_leg()
 
     r = res[primary]
     # the dominant kernel of the headline path (largest share of the solve's time)

@@ -8,7 +8,12 @@
 //
 // the forward weights applied in reverse time (full or short memory: the
 // window of offsets is the same in both directions), so the sum over the mu
-// history is the forward history sum at reverse step n-1-k.  Gradients with dt
+// history is the forward history sum at reverse step n-1-k (adaptive memory
+// uses the schedule's transpose instead).  On the blocked path that sum, like
+// the forward one, takes the mu rows before its block of reverse steps as one
+// matrix-core product per block (the Toeplitz kernel over the mu history) and
+// the rows since the block's start by the GEMV; G below is formed the same way
+// with the d psi / d gamma tables over the delta history.  Gradients with dt
 // and dx fixed, S[k] = sum psi(m) delta[k-m] and G[k] = sum d psi/d gamma (m)
 // delta[k-m]:
 //   dL/dalpha = (r/alpha) sum_k <lam[k+1], S[k]>
@@ -38,7 +43,8 @@ __device__ __forceinline__ double adj_dfdrate(int rxn, double u) {
 
 __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
     const double *__restrict__ lam1, double *__restrict__ lam0, float *__restrict__ Mrow,
-    const double *__restrict__ partial, int nsplit, int64_t P, int ndim, int nx, int ny, int nz,
+    const double *__restrict__ partial, int nsplit, const double *__restrict__ base, int64_t P,
+    int ndim, int nx, int ny, int nz,
     double r, double dt, int rxn, double rate, const double *__restrict__ uk,
     const double *__restrict__ Sk, const double *__restrict__ Gk, double *__restrict__ grad) {
     __shared__ double red[3][kAdjThreads];
@@ -70,6 +76,7 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
         }
         const double mu = r * lap;
         double A = mu;
+        if (base) A += base[p];
         int q = 0;
         for (; q + 8 <= nsplit; q += 8) {
             double v[8];
@@ -105,12 +112,13 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
 int adjoint_groups(int64_t P) { return (int)((P + kAdjThreads - 1) / kAdjThreads); }
 
 void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, float *Mrow,
-                           const double *partial, int nsplit, const double *uk, const double *Sk,
-                           const double *Gk, double *grad, hipStream_t s) {
+                           const double *partial, int nsplit, const double *base,
+                           const double *uk, const double *Sk, const double *Gk, double *grad,
+                           hipStream_t s) {
     const gl_problem &p = pb.p;
     GL_LAUNCH(adjoint_update_kernel, dim3((unsigned)adjoint_groups(pb.P)), dim3(kAdjThreads), 0, s,
-              lam1, lam0, Mrow, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, p.nz, pb.r, p.dt,
-              p.rxn, p.rxn_rate, uk, Sk, Gk, grad);
+              lam1, lam0, Mrow, partial, nsplit, base, pb.P, p.ndim, p.nx, p.ny, p.nz, pb.r,
+              p.dt, p.rxn, p.rxn_rate, uk, Sk, Gk, grad);
 }
 
 // One workgroup: lane t sums entries t, t + 256, ... in order, then a fixed tree.

@@ -43,6 +43,12 @@ struct gl_ctx {
     double *adj_grad = nullptr;  // per step and workgroup partial dot products, 3 each
     gl::Run *adj_runs = nullptr;  // adaptive memory: the transposed schedule's runs
     size_t adj_runs_cap = 0;
+    // blocked adjoint (Toeplitz path): sums over the rows before a block, of the mu history
+    // with psi (reverse sweep) and of the delta history with d psi / d gamma (recompute), and
+    // the run lists m = 1 .. min(c, L) for the rows after a block's start
+    double *adj_oldA = nullptr, *adj_oldG = nullptr;  // B x max P each
+    int64_t adj_oldA_r0 = -1, adj_oldG_k0 = -1;
+    gl::Run *adj_recent = nullptr;                     // B entries
     int64_t maxP = 0, maxld = 0;
     int B = 256;             // block length of the Toeplitz path
     int B2 = 0;              // sub-block length inside a block (0: one level)
@@ -483,9 +489,9 @@ gl_status step_gemv(gl_ctx *ctx) {
 // (base[b] +) out[b] = sum_{j_lo <= j < j_hi} psi(k_out + b - j) hist[j] for b < BM, on the
 // matrix cores (FP32 chunk products summed in FP64; one chunk is written by the product
 // kernel itself).
-gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int BM,
-                     int64_t k_out, int64_t j_lo, int64_t j_hi, double *out, const double *base,
-                     int gemm_id, int reduce_id) {
+gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const uint16_t *tab, const float *hist,
+                     int64_t ld, int BM, int64_t k_out, int64_t j_lo, int64_t j_hi, double *out,
+                     const double *base, int gemm_id, int reduce_id) {
     if (j_hi <= j_lo)  // no rows in the window: the sums are the base (or zero)
         return timed(ctx, reduce_id, [&] {
             gl::launch_old_reduce(ctx->tpart, 0, BM, pb.P, out, base, ctx->stream);
@@ -496,7 +502,7 @@ gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld
         return fail(ctx, GL_EINVAL, "internal: %d chunk products of %d x %lld exceed the buffer",
                     nchunk, BM, (long long)pb.P);
     gl_status st = timed(ctx, gemm_id, [&] {
-        gl::launch_toeplitz_gemm(BM, hist, ld, pb.P, pb.psi_tab, pb.tab_len, k_out, j_lo, j_hi,
+        gl::launch_toeplitz_gemm(BM, hist, ld, pb.P, tab, pb.tab_len, k_out, j_lo, j_hi,
                                  kchunk, ctx->tpart, out, base, ctx->stream);
     });
     if (st != GL_OK || nchunk <= 1) return st;
@@ -516,7 +522,8 @@ int64_t window_lo(const gl_ctx *ctx, int64_t k_out) {
 // old[b] = sum_{j < k0} psi(k0 + b - j) hist[j] for b < B.
 gl_status block_old(gl_ctx *ctx, gl::Problem &pb, const float *hist, int64_t ld, int64_t k0,
                     double *old) {
-    return block_sums(ctx, pb, hist, ld, ctx->B, k0, window_lo(ctx, k0), k0, old, nullptr,
+    return block_sums(ctx, pb, pb.psi_tab, hist, ld, ctx->B, k0, window_lo(ctx, k0), k0, old,
+                      nullptr,
                       GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE);
 }
 
@@ -549,7 +556,7 @@ gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
     }
     if (k1 > k0 && pb.old2_k1 != k1) {
         // Old2 holds Old (rows of the sub-block's steps) + the product over rows k0 .. k1-1
-        if ((st = block_sums(ctx, pb, pb.H, pb.ld, ctx->B2, k1,
+        if ((st = block_sums(ctx, pb, pb.psi_tab, pb.H, pb.ld, ctx->B2, k1,
                              std::max(k0, window_lo(ctx, k1)), k1, pb.old2,
                              k0 > 0 ? pb.old + (k1 - k0) * pb.P : nullptr, GL_KERNEL_SUBBLOCK,
                              GL_KERNEL_SUB_REDUCE)) != GL_OK)
@@ -640,6 +647,11 @@ gl_status step_toeplitz(gl_ctx *ctx, int64_t limit, int64_t *done) {
 // Recomputes u[ks..ke] of one problem from the snapshot u[ks] with the forward's own
 // kernels (bit-identical to the forward run), keeping u[k] in adj_u, the step sums S[k]
 // in adj_S and the sums G[k] with d psi / d gamma in adj_G (k in [ks, ke)).
+// Terms (m = 0 included) of the run adj_recent[c]: offsets 0 .. min(c, L).
+int64_t recent_terms(const gl_ctx *ctx, int64_t c) {
+    return (ctx->opt.mem_mode == GL_MEM_SHORT ? std::min<int64_t>(c, ctx->opt.short_L) : c) + 1;
+}
+
 gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke) {
     const int64_t P = pb.P;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_u, pb.snap + (ks / ctx->C) * P, P * sizeof(double),
@@ -672,6 +684,26 @@ gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke
             gl::launch_update(pb, u, nullptr, un, nullptr, S, ctx->partial, nsplit, ctx->stream);
         }
         // G[k] = sum over the same terms of d psi / d gamma (m) delta[k-m]; the m = 0 weight is 0
+        if (toep) {
+            // blocked: the rows before k's block by the matrix-core product with the d psi
+            // tables (once per block), the c = k - k_a rows since by the GEMV on that base
+            const int64_t ka = k - k % ctx->B, c = k - ka;
+            if (ctx->adj_oldG_k0 != ka) {
+                if ((st = block_sums(ctx, pb, pb.dpsi_tab, pb.H, pb.ld, ctx->B, ka,
+                                     window_lo(ctx, ka), ka, ctx->adj_oldG, nullptr,
+                                     GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE)) != GL_OK)
+                    return st;
+                ctx->adj_oldG_k0 = ka;
+            }
+            const int64_t Tr = recent_terms(ctx, c);
+            const int ns = gl::gemv_splits(Tr - 1, P, pb.gemv_groups);
+            if (ns > 0)
+                gl::launch_hist_gemv(pb.H, pb.ld, P, pb.dpsi, ctx->adj_recent + c, 1, k, 1, Tr,
+                                     ns, false, ctx->partial, ctx->stream);
+            gl::launch_reduce_partials(ctx->partial, ns, P, ctx->adj_oldG + c * P,
+                                       ctx->adj_G + i * P, ctx->stream);
+            continue;
+        }
         if (nsplit > 0)
             gl::launch_hist_gemv(pb.H, pb.ld, P, pb.dpsi, ctx->d_runs + rb, nruns, k, 1, T, nsplit,
                                  false, ctx->partial, ctx->stream);
@@ -686,9 +718,14 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
     if (ctx->adj_M) return GL_OK;
     const int64_t C = ctx->C, n = ctx->opt.max_steps;
     const int groups = gl::adjoint_groups(ctx->maxP);
-    const size_t need = ((size_t)n * ctx->maxld) * sizeof(float) +
-                        ((size_t)(3 * C + 1) * ctx->maxP + 2 * (size_t)ctx->maxP +
-                         (size_t)n * groups * 3) * sizeof(double);
+    const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
+    size_t need = ((size_t)n * ctx->maxld) * sizeof(float) +
+                  ((size_t)(3 * C + 1) * ctx->maxP + 2 * (size_t)ctx->maxP +
+                   (size_t)n * groups * 3) * sizeof(double);
+    if (toep) {
+        need += 2 * (size_t)ctx->B * ctx->maxP * sizeof(double);
+        for (const gl::Problem &pb : ctx->probs) need += 16 * (size_t)pb.tab_len * sizeof(uint16_t);
+    }
     size_t free_b = 0, total_b = 0;
     HIP_TRY(ctx, hipMemGetInfo(&free_b, &total_b));
     if (need + (size_t)(256u << 20) > free_b)
@@ -702,6 +739,30 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
     if ((st = dev_alloc(ctx, &ctx->adj_lam[0], ctx->maxP))) return st;
     if ((st = dev_alloc(ctx, &ctx->adj_lam[1], ctx->maxP))) return st;
     if ((st = dev_alloc(ctx, &ctx->adj_grad, (size_t)n * groups * 3))) return st;
+    if (toep) {
+        if ((st = dev_alloc(ctx, &ctx->adj_oldA, (size_t)ctx->B * ctx->maxP))) return st;
+        if ((st = dev_alloc(ctx, &ctx->adj_oldG, (size_t)ctx->B * ctx->maxP))) return st;
+        // run c: offsets m = 0 .. min(c, L) (the sums skip m = 0, added by the update)
+        std::vector<gl::Run> recent(ctx->B);
+        for (int c = 0; c < ctx->B; ++c) {
+            int64_t cnt = c;
+            if (ctx->opt.mem_mode == GL_MEM_SHORT) cnt = std::min<int64_t>(cnt, ctx->opt.short_L);
+            recent[c] = gl::Run{0, (int32_t)cnt + 1, 1, 1};
+        }
+        if ((st = dev_alloc(ctx, &ctx->adj_recent, recent.size()))) return st;
+        HIP_TRY(ctx, hipMemcpy(ctx->adj_recent, recent.data(), recent.size() * sizeof(gl::Run),
+                               hipMemcpyHostToDevice));
+        // d psi / d gamma tables (zero past a short-memory window, as the psi tables)
+        const int64_t npsi = ctx->opt.max_steps + gl::kMaxBlock + 1;
+        const int64_t nkeep = ctx->opt.mem_mode == GL_MEM_SHORT
+                                  ? std::min(npsi, ctx->opt.short_L + 1)
+                                  : npsi;
+        for (gl::Problem &pb : ctx->probs) {
+            if ((st = dev_alloc(ctx, &pb.dpsi_tab, 16 * (size_t)pb.tab_len))) return st;
+            gl::launch_psi_tables(pb.dpsi, nkeep, pb.tab_len, pb.dpsi_tab, ctx->stream);
+        }
+        HIP_TRY(ctx, hipGetLastError());
+    }
     return GL_OK;
 }
 
@@ -742,11 +803,13 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
     const gl::Schedule *ts = nullptr;
     const gl::Run *truns = nullptr;
     if ((st = reverse_schedule(ctx, n, &tsched, &ts, &truns)) != GL_OK) return st;
+    const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
     for (size_t ip = 0; ip < ctx->probs.size(); ++ip) {
         gl::Problem &pb = ctx->probs[ip];
         const int64_t P = pb.P;
         const int groups = gl::adjoint_groups(P);
         int cur = 0;
+        ctx->adj_oldA_r0 = ctx->adj_oldG_k0 = -1;  // block sums of this problem's histories
         HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_lam[0], dL_duT + pb.offset, P * sizeof(double),
                                     hipMemcpyDeviceToDevice, ctx->stream));
         for (int64_t seg = (n - 1) / C; seg >= 0; --seg) {
@@ -754,16 +817,34 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
             if ((st = adjoint_recompute(ctx, pb, ks, ke)) != GL_OK) return st;
             for (int64_t k = ke - 1; k >= ks; --k) {
                 const int64_t rho = n - 1 - k;  // reverse step: the reverse schedule at rho
-                const int64_t rb = ts->run_begin[rho];
-                const int nruns = (int)(ts->run_begin[rho + 1] - rb);
-                const int64_t T = ts->terms[rho];
+                const double *base = nullptr;
+                int64_t rb = ts->run_begin[rho], T = ts->terms[rho];
+                int nruns = (int)(ts->run_begin[rho + 1] - rb);
+                const gl::Run *runs = truns + rb;
+                if (toep) {
+                    // blocked: the mu rows before rho's block by the matrix-core product (once
+                    // per block, the forward's Toeplitz structure in reverse time), the c rows
+                    // since by the GEMV on that base
+                    const int64_t r0 = rho - rho % ctx->B, c = rho - r0;
+                    if (ctx->adj_oldA_r0 != r0) {
+                        if ((st = block_sums(ctx, pb, pb.psi_tab, ctx->adj_M, pb.ld, ctx->B, r0,
+                                             window_lo(ctx, r0), r0, ctx->adj_oldA, nullptr,
+                                             GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE)) != GL_OK)
+                            return st;
+                        ctx->adj_oldA_r0 = r0;
+                    }
+                    base = ctx->adj_oldA + c * P;
+                    runs = ctx->adj_recent + c;
+                    nruns = 1;
+                    T = recent_terms(ctx, c);
+                }
                 const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
                 if (nsplit > 0)
-                    gl::launch_hist_gemv(ctx->adj_M, pb.ld, P, pb.psi, truns + rb, nruns, rho, 1,
-                                         T, nsplit, false, ctx->partial, ctx->stream);
+                    gl::launch_hist_gemv(ctx->adj_M, pb.ld, P, pb.psi, runs, nruns, rho, 1, T,
+                                         nsplit, false, ctx->partial, ctx->stream);
                 const int64_t i = k - ks;
                 gl::launch_adjoint_update(pb, ctx->adj_lam[cur], ctx->adj_lam[cur ^ 1],
-                                          ctx->adj_M + rho * pb.ld, ctx->partial, nsplit,
+                                          ctx->adj_M + rho * pb.ld, ctx->partial, nsplit, base,
                                           ctx->adj_u + i * P, ctx->adj_S + i * P,
                                           ctx->adj_G + i * P, ctx->adj_grad + k * groups * 3,
                                           ctx->stream);

@@ -80,6 +80,7 @@ struct Problem {
     int cur = 0;             // u[cur] holds the current step
     // blocked Toeplitz path
     uint16_t *psi_tab = nullptr;  // BF16 hi/lo weight tables, 2 x 8 shifted copies of tab_len
+    uint16_t *dpsi_tab = nullptr; // the same for d psi / d gamma (blocked adjoint, lazily)
     int64_t tab_len = 0;
     double *old = nullptr;        // [B x P] FP64 sums over the rows before the current block
     int64_t old_k0 = -1;          // block start old[] belongs to (-1: none)
@@ -230,12 +231,13 @@ void launch_update(const Problem &pb, const double *u, const double *base, doubl
                    float *Hk, double *S_out, const double *partial, int nsplit, hipStream_t s);
 
 // ---- adjoint
-// One reverse step: mu = r stencil(lam1); A = mu + sum_s partial[s];
+// One reverse step: mu = r stencil(lam1); A = mu (+ base) + sum_s partial[s];
 // lam0 = lam1 + dt f'(uk) lam1 + A; Mrow = (float) mu; and per-workgroup partial sums
 // of lam1 * Sk, lam1 * Gk, lam1 * df/drate(uk) into grad[3 * blockIdx].
 void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, float *Mrow,
-                           const double *partial, int nsplit, const double *uk, const double *Sk,
-                           const double *Gk, double *grad, hipStream_t s);
+                           const double *partial, int nsplit, const double *base,
+                           const double *uk, const double *Sk, const double *Gk, double *grad,
+                           hipStream_t s);
 // Workgroups of one adjoint update launch for P points.
 int adjoint_groups(int64_t P);
 // dparams[0..2] = {dL/dalpha, dL/dgamma, dL/drate} from the per-step partial sums
