@@ -72,3 +72,23 @@ def test_forward_and_transposed_schedules_match_oracle(probe, mem):
         assert seq == sorted(seq) and seq[0] == 0 and got[0] == 1   # ascending, m = 0 first
         if mem["mode"] != "adaptive":   # full and short memory are their own transposes
             assert got == tables["F"][rho][0], rho
+
+
+def test_random_settings_match_oracle(probe):
+    # seeded random memory settings and run lengths, forward and transposed tables
+    import numpy as np
+    rng = np.random.default_rng(77)
+    for _ in range(24):
+        mode = ["full", "short", "adaptive"][int(rng.integers(3))]
+        mem = W.memory(mode, L=int(rng.integers(0, 60)), a=int(rng.integers(2, 9)),
+                       rule=["partition", "literal", "unit_stride"][int(rng.integers(3))])
+        n = int(rng.integers(1, 260))
+        tables = run_probe(probe, mem, n)
+        trans = defaultdict(lambda: defaultdict(float))
+        for k in range(n):
+            ms, cs = oracle.schedule(mem, k)
+            assert tables["F"][k][0] == {int(m): int(c) for m, c in zip(ms, cs)}, (mem, n, k)
+            for m, c in zip(ms, cs):
+                trans[n - 1 - (k - int(m))][int(m)] += c
+        for rho in range(n):
+            assert tables["T"][rho][0] == {m: int(c) for m, c in trans[rho].items()}, (mem, n, rho)
