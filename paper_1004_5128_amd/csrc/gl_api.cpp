@@ -43,11 +43,11 @@ struct gl_ctx {
     double *adj_grad = nullptr;  // per step and workgroup partial dot products, 3 each
     gl::Run *adj_runs = nullptr;  // adaptive memory: the transposed schedule's runs
     size_t adj_runs_cap = 0;
-    // blocked adjoint (Toeplitz path): sums over the rows before a block, of the mu history
-    // with psi (reverse sweep) and of the delta history with d psi / d gamma (recompute), and
-    // the run lists m = 1 .. min(c, L) for the rows after a block's start
+    // blocked adjoint (Toeplitz path): the sums over the mu rows before a block of reverse
+    // steps (psi), the sums G of a block's steps over the delta history (d psi / d gamma), and
+    // the run lists m = 0 .. min(c, L) for the mu rows after a block's start
     double *adj_oldA = nullptr, *adj_oldG = nullptr;  // B x max P each
-    int64_t adj_oldA_r0 = -1, adj_oldG_k0 = -1;
+    int64_t adj_oldA_r0 = -1;
     gl::Run *adj_recent = nullptr;                     // B entries
     int64_t maxP = 0, maxld = 0;
     int B = 256;             // block length of the Toeplitz path
@@ -501,10 +501,15 @@ gl_status block_sums(gl_ctx *ctx, gl::Problem &pb, const uint16_t *tab, const fl
     if (nchunk > 1 && (int64_t)nchunk * BM * pb.P > ctx->tpart_len)
         return fail(ctx, GL_EINVAL, "internal: %d chunk products of %d x %lld exceed the buffer",
                     nchunk, BM, (long long)pb.P);
+    bool launched = false;
     gl_status st = timed(ctx, gemm_id, [&] {
-        gl::launch_toeplitz_gemm(BM, hist, ld, pb.P, tab, pb.tab_len, k_out, j_lo, j_hi,
-                                 kchunk, ctx->tpart, out, base, ctx->stream);
+        launched = gl::launch_toeplitz_gemm(BM, hist, ld, pb.P, tab, pb.tab_len, k_out, j_lo,
+                                            j_hi, kchunk, ctx->tpart, out, base, ctx->stream);
     });
+    if (st == GL_OK && !launched)
+        return fail(ctx, GL_EINVAL, "internal: Toeplitz product over rows [%lld, %lld) for step "
+                    "%lld, %d rows out, refused", (long long)j_lo, (long long)j_hi,
+                    (long long)k_out, BM);
     if (st != GL_OK || nchunk <= 1) return st;
     return timed(ctx, reduce_id, [&] {
         gl::launch_old_reduce(ctx->tpart, nchunk, BM, pb.P, out, base, ctx->stream);
@@ -667,7 +672,7 @@ gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke
             k += s;
         }
     }
-    for (int64_t k = ks; k < ke; ++k) {
+    for (int64_t k = ks; k < ke && !toep; ++k) {
         const int64_t i = k - ks;
         const double *u = ctx->adj_u + i * P;
         double *un = ctx->adj_u + (i + 1) * P;
@@ -676,39 +681,36 @@ gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke
         const int nruns = (int)(ctx->sched.run_begin[k + 1] - rb);
         const int64_t T = ctx->sched.terms[k];
         const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
-        if (!toep) {
-            const bool reverse = ctx->tune.serpentine && (k & 1);
-            if (nsplit > 0)
-                gl::launch_hist_gemv(pb.H, pb.ld, P, pb.psi, ctx->d_runs + rb, nruns, k, 1, T,
-                                     nsplit, reverse, ctx->partial, ctx->stream);
-            gl::launch_update(pb, u, nullptr, un, nullptr, S, ctx->partial, nsplit, ctx->stream);
-        }
+        const bool reverse = ctx->tune.serpentine && (k & 1);
+        if (nsplit > 0)
+            gl::launch_hist_gemv(pb.H, pb.ld, P, pb.psi, ctx->d_runs + rb, nruns, k, 1, T, nsplit,
+                                 reverse, ctx->partial, ctx->stream);
+        gl::launch_update(pb, u, nullptr, un, nullptr, S, ctx->partial, nsplit, ctx->stream);
         // G[k] = sum over the same terms of d psi / d gamma (m) delta[k-m]; the m = 0 weight is 0
-        if (toep) {
-            // blocked: the rows before k's block by the matrix-core product with the d psi
-            // tables (once per block), the c = k - k_a rows since by the GEMV on that base
-            const int64_t ka = k - k % ctx->B, c = k - ka;
-            if (ctx->adj_oldG_k0 != ka) {
-                if ((st = block_sums(ctx, pb, pb.dpsi_tab, pb.H, pb.ld, ctx->B, ka,
-                                     window_lo(ctx, ka), ka, ctx->adj_oldG, nullptr,
-                                     GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE)) != GL_OK)
-                    return st;
-                ctx->adj_oldG_k0 = ka;
-            }
-            const int64_t Tr = recent_terms(ctx, c);
-            const int ns = gl::gemv_splits(Tr - 1, P, pb.gemv_groups);
-            if (ns > 0)
-                gl::launch_hist_gemv(pb.H, pb.ld, P, pb.dpsi, ctx->adj_recent + c, 1, k, 1, Tr,
-                                     ns, false, ctx->partial, ctx->stream);
-            gl::launch_reduce_partials(ctx->partial, ns, P, ctx->adj_oldG + c * P,
-                                       ctx->adj_G + i * P, ctx->stream);
-            continue;
-        }
         if (nsplit > 0)
             gl::launch_hist_gemv(pb.H, pb.ld, P, pb.dpsi, ctx->d_runs + rb, nruns, k, 1, T, nsplit,
                                  false, ctx->partial, ctx->stream);
         gl::launch_reduce_partials(ctx->partial, nsplit, P, nullptr, ctx->adj_G + i * P,
                                    ctx->stream);
+    }
+    if (toep) {
+        // blocked: G for the B steps of each block k_a .. k_a + B - 1 in one matrix-core
+        // product with the d psi / d gamma tables over every history row before the block's
+        // end: d psi / d gamma (0) = 0 and the tables are zero for m < 0, so row j adds to the
+        // steps after it only, and every row is already in the history (the forward wrote
+        // rows 0 .. n - 1); the segment's steps are copied out of the block's sums
+        const int64_t n = ctx->k;
+        for (int64_t ka = ks - ks % ctx->B; ka < ke; ka += ctx->B) {
+            if ((st = block_sums(ctx, pb, pb.dpsi_tab, pb.H, pb.ld, ctx->B, ka,
+                                 window_lo(ctx, ka), std::min(ka + ctx->B, n), ctx->adj_oldG,
+                                 nullptr, GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE)) != GL_OK)
+                return st;
+            const int64_t k_lo = std::max(ka, ks), k_hi = std::min(ka + ctx->B, ke);
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_G + (k_lo - ks) * P,
+                                        ctx->adj_oldG + (k_lo - ka) * P,
+                                        (size_t)(k_hi - k_lo) * P * sizeof(double),
+                                        hipMemcpyDeviceToDevice, ctx->stream));
+        }
     }
     HIP_TRY(ctx, hipGetLastError());
     return GL_OK;
@@ -809,7 +811,7 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
         const int64_t P = pb.P;
         const int groups = gl::adjoint_groups(P);
         int cur = 0;
-        ctx->adj_oldA_r0 = ctx->adj_oldG_k0 = -1;  // block sums of this problem's histories
+        ctx->adj_oldA_r0 = -1;  // block sums of this problem's mu history
         HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_lam[0], dL_duT + pb.offset, P * sizeof(double),
                                     hipMemcpyDeviceToDevice, ctx->stream));
         for (int64_t seg = (n - 1) / C; seg >= 0; --seg) {

@@ -153,7 +153,8 @@ struct Tuning {
 constexpr int64_t kMaxChunkWgs = 4;
 
 // ---- blocked Toeplitz path
-constexpr int kPsiPad = 128;  // zero entries before psi(0) in the BF16 weight tables
+constexpr int kPsiPad = 1024;  // zero entries before psi(0) in the BF16 weight tables: a
+                               // product may take rows up to BM past k0 (weights psi(m < 0) = 0)
 constexpr int kMaxBlock = 512;
 constexpr int kMaxTK = 128;   // history rows per Toeplitz K step, at most (chunks are multiples)
 
@@ -166,9 +167,12 @@ int toeplitz_chunks(int64_t rows, int64_t kchunk);
 
 // out[c][b][p] (FP32) = sum over rows j in chunk c of [j_lo, j_hi) of
 // T[b][j] H[j * ld + p] with T[b][j] = psi(k0 + b - j), b < BM, three BF16 products
-// (j_hi <= k0).  With one chunk and direct != nullptr the FP64 result (what the chunk
+// (j_hi <= k0 + BM).  With one chunk and direct != nullptr the FP64 result (what the chunk
 // reduction below gives, plus base[b][p] when base != nullptr) goes to direct[b][p] instead.
-void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
+// Returns false, launching nothing, when k0 or j_lo is not a multiple of 32, j_hi > k0 + BM,
+// kchunk is not a multiple of kMaxTK or BM is not a supported block length.  Rows j >= k0 + b
+// have weight psi(k0 + b - j <= 0): psi(0) = 1 at j = k0 + b, zero past it.
+bool launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
                           int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
                           float *out, double *direct, const double *base, hipStream_t s);
 

@@ -322,15 +322,16 @@ int toeplitz_chunks(int64_t rows, int64_t kchunk) {
     return rows <= 0 ? 0 : (int)((rows + kchunk - 1) / kchunk);
 }
 
-void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
+bool launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const uint16_t *tab,
                           int64_t tab_len, int64_t k0, int64_t j_lo, int64_t j_hi, int64_t kchunk,
                           float *out, double *direct, const double *base, hipStream_t s) {
+    // K steps start at j_lo; with k0 and j_lo multiples of 32 and j_hi <= k0 + BM every step
+    // has k0 - jt > -BM, which with the zero pad of kPsiPad >= kMaxBlock + kMaxTK + 8 entries
+    // keeps the staged weight words inside the tables
+    static_assert(kPsiPad >= kMaxBlock + kMaxTK + 8, "the tables' zero pad covers BM + a K step");
+    if (k0 % 32 != 0 || j_lo % 32 != 0 || j_hi > k0 + BM || kchunk % kMaxTK != 0) return false;
     const int nchunk = toeplitz_chunks(j_hi - j_lo, kchunk);
-    if (nchunk == 0) return;
-    // K steps start at j_lo; with k0 and j_lo multiples of 32 every step has k0 - jt >= 32,
-    // which (with the zero pad of kPsiPad >= TK entries) keeps the staged weight words inside
-    // the tables
-    if (k0 % 32 != 0 || j_lo % 32 != 0 || j_hi > k0 || kchunk % kMaxTK != 0) return;
+    if (nchunk == 0) return true;
     if (nchunk > 1) direct = nullptr;  // the chunk reduction writes the sums
     dim3 grid((unsigned)((P + kTN - 1) / kTN), (unsigned)nchunk);
     const u32x4_t *t = reinterpret_cast<const u32x4_t *>(tab);
@@ -346,9 +347,10 @@ void launch_toeplitz_gemm(int BM, const float *H, int64_t ld, int64_t P, const u
         GL_GEMM_CASE(256)
         GL_GEMM_CASE(512)
         default:
-            break;
+            return false;
     }
 #undef GL_GEMM_CASE
+    return true;
 }
 
 __global__ void old_reduce_kernel(const float *__restrict__ part, int nchunk, int64_t BP,
