@@ -43,8 +43,9 @@ __device__ __forceinline__ double adj_dfdrate(int rxn, double u) {
 
 __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
     const double *__restrict__ lam1, double *__restrict__ lam0, float *__restrict__ Mrow,
-    const double *__restrict__ partial, int nsplit, const double *__restrict__ base, int64_t P,
-    int ndim, int nx, int ny, int nz,
+    const double *__restrict__ partial, int nsplit, const double *__restrict__ base,
+    const float *__restrict__ rows, int64_t ld, int nrows, int first,
+    const double *__restrict__ psi, int64_t P, int ndim, int nx, int ny, int nz,
     double r, double dt, int rxn, double rate, const double *__restrict__ uk,
     const double *__restrict__ Sk, const double *__restrict__ Gk, double *__restrict__ grad) {
     __shared__ double red[3][kAdjThreads];
@@ -86,6 +87,15 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
             for (int i = 0; i < 8; ++i) A += v[i];
         }
         for (; q < nsplit; ++q) A += partial[(int64_t)q * P + p];
+        // the mu rows since the sub-block's start, row t at offset nrows - t, ascending t
+        for (int t = first; t < nrows; t += 8) {
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = rows[(int64_t)min(t + e, nrows - 1) * ld + p];
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (t + e < nrows) A = fma(psi[nrows - t - e], (double)v[e], A);
+        }
         const double l1 = lam1[p];
         const double u = uk[p];
         lam0[p] = l1 + dt * adj_dfdu(rxn, rate, u) * l1 + A;
@@ -113,12 +123,12 @@ int adjoint_groups(int64_t P) { return (int)((P + kAdjThreads - 1) / kAdjThreads
 
 void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, float *Mrow,
                            const double *partial, int nsplit, const double *base,
-                           const double *uk, const double *Sk, const double *Gk, double *grad,
-                           hipStream_t s) {
+                           const float *rows, int nrows, int first, const double *uk,
+                           const double *Sk, const double *Gk, double *grad, hipStream_t s) {
     const gl_problem &p = pb.p;
     GL_LAUNCH(adjoint_update_kernel, dim3((unsigned)adjoint_groups(pb.P)), dim3(kAdjThreads), 0, s,
-              lam1, lam0, Mrow, partial, nsplit, base, pb.P, p.ndim, p.nx, p.ny, p.nz, pb.r,
-              p.dt, p.rxn, p.rxn_rate, uk, Sk, Gk, grad);
+              lam1, lam0, Mrow, partial, nsplit, base, rows, pb.ld, nrows, first, pb.psi, pb.P,
+              p.ndim, p.nx, p.ny, p.nz, pb.r, p.dt, p.rxn, p.rxn_rate, uk, Sk, Gk, grad);
 }
 
 // One workgroup: lane t sums entries t, t + 256, ... in order, then a fixed tree.

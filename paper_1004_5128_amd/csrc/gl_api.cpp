@@ -47,7 +47,8 @@ struct gl_ctx {
     // steps (psi), the sums G of a block's steps over the delta history (d psi / d gamma), and
     // the run lists m = 0 .. min(c, L) for the mu rows after a block's start
     double *adj_oldA = nullptr, *adj_oldG = nullptr;  // B x max P each
-    int64_t adj_oldA_r0 = -1;
+    double *adj_oldA2 = nullptr;                       // B2 x max P (sub-block sums)
+    int64_t adj_oldA_r0 = -1, adj_oldA2_r1 = -1;
     gl::Run *adj_recent = nullptr;                     // B entries
     int64_t maxP = 0, maxld = 0;
     int B = 256;             // block length of the Toeplitz path
@@ -725,7 +726,7 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
                   ((size_t)(3 * C + 1) * ctx->maxP + 2 * (size_t)ctx->maxP +
                    (size_t)n * groups * 3) * sizeof(double);
     if (toep) {
-        need += 2 * (size_t)ctx->B * ctx->maxP * sizeof(double);
+        need += (2 * (size_t)ctx->B + ctx->B2) * ctx->maxP * sizeof(double);
         for (const gl::Problem &pb : ctx->probs) need += 16 * (size_t)pb.tab_len * sizeof(uint16_t);
     }
     size_t free_b = 0, total_b = 0;
@@ -744,6 +745,8 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
     if (toep) {
         if ((st = dev_alloc(ctx, &ctx->adj_oldA, (size_t)ctx->B * ctx->maxP))) return st;
         if ((st = dev_alloc(ctx, &ctx->adj_oldG, (size_t)ctx->B * ctx->maxP))) return st;
+        if (ctx->B2 && (st = dev_alloc(ctx, &ctx->adj_oldA2, (size_t)ctx->B2 * ctx->maxP)))
+            return st;
         // run c: offsets m = 0 .. min(c, L) (the sums skip m = 0, added by the update)
         std::vector<gl::Run> recent(ctx->B);
         for (int c = 0; c < ctx->B; ++c) {
@@ -811,7 +814,7 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
         const int64_t P = pb.P;
         const int groups = gl::adjoint_groups(P);
         int cur = 0;
-        ctx->adj_oldA_r0 = -1;  // block sums of this problem's mu history
+        ctx->adj_oldA_r0 = ctx->adj_oldA2_r1 = -1;  // block sums of this problem's mu history
         HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_lam[0], dL_duT + pb.offset, P * sizeof(double),
                                     hipMemcpyDeviceToDevice, ctx->stream));
         for (int64_t seg = (n - 1) / C; seg >= 0; --seg) {
@@ -823,22 +826,46 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
                 int64_t rb = ts->run_begin[rho], T = ts->terms[rho];
                 int nruns = (int)(ts->run_begin[rho + 1] - rb);
                 const gl::Run *runs = truns + rb;
+                const float *rows = nullptr;
+                int nrows = 0, first = 0;
                 if (toep) {
-                    // blocked: the mu rows before rho's block by the matrix-core product (once
-                    // per block, the forward's Toeplitz structure in reverse time), the c rows
-                    // since by the GEMV on that base
-                    const int64_t r0 = rho - rho % ctx->B, c = rho - r0;
+                    // blocked, as the forward in reverse time: the mu rows before rho's block by
+                    // the matrix-core product (once per block); with sub-blocks, the block's
+                    // rows before rho's sub-block by a second product on that base (once per
+                    // sub-block) and the <= B2 - 1 rows since summed by the update itself;
+                    // without, the rows since the block's start by the GEMV
+                    const int64_t r0 = rho - rho % ctx->B;
                     if (ctx->adj_oldA_r0 != r0) {
                         if ((st = block_sums(ctx, pb, pb.psi_tab, ctx->adj_M, pb.ld, ctx->B, r0,
                                              window_lo(ctx, r0), r0, ctx->adj_oldA, nullptr,
                                              GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE)) != GL_OK)
                             return st;
                         ctx->adj_oldA_r0 = r0;
+                        ctx->adj_oldA2_r1 = -1;
                     }
-                    base = ctx->adj_oldA + c * P;
-                    runs = ctx->adj_recent + c;
-                    nruns = 1;
-                    T = recent_terms(ctx, c);
+                    if (ctx->B2) {
+                        const int64_t r1 = rho - rho % ctx->B2, c = rho - r1;
+                        if (r1 > r0 && ctx->adj_oldA2_r1 != r1) {
+                            if ((st = block_sums(ctx, pb, pb.psi_tab, ctx->adj_M, pb.ld, ctx->B2,
+                                                 r1, std::max(r0, window_lo(ctx, r1)), r1,
+                                                 ctx->adj_oldA2, ctx->adj_oldA + (r1 - r0) * P,
+                                                 GL_KERNEL_SUBBLOCK, GL_KERNEL_SUB_REDUCE)) != GL_OK)
+                                return st;
+                            ctx->adj_oldA2_r1 = r1;
+                        }
+                        base = (r1 > r0 ? ctx->adj_oldA2 : ctx->adj_oldA) + c * P;
+                        rows = ctx->adj_M + r1 * pb.ld;
+                        nrows = (int)c;
+                        if (ctx->opt.mem_mode == GL_MEM_SHORT)
+                            first = (int)std::max<int64_t>(0, c - ctx->opt.short_L);
+                        T = 1;  // no GEMV terms
+                    } else {
+                        const int64_t c = rho - r0;
+                        base = ctx->adj_oldA + c * P;
+                        runs = ctx->adj_recent + c;
+                        nruns = 1;
+                        T = recent_terms(ctx, c);
+                    }
                 }
                 const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
                 if (nsplit > 0)
@@ -847,9 +874,9 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
                 const int64_t i = k - ks;
                 gl::launch_adjoint_update(pb, ctx->adj_lam[cur], ctx->adj_lam[cur ^ 1],
                                           ctx->adj_M + rho * pb.ld, ctx->partial, nsplit, base,
-                                          ctx->adj_u + i * P, ctx->adj_S + i * P,
-                                          ctx->adj_G + i * P, ctx->adj_grad + k * groups * 3,
-                                          ctx->stream);
+                                          rows, nrows, first, ctx->adj_u + i * P,
+                                          ctx->adj_S + i * P, ctx->adj_G + i * P,
+                                          ctx->adj_grad + k * groups * 3, ctx->stream);
                 cur ^= 1;
             }
             HIP_TRY(ctx, hipGetLastError());

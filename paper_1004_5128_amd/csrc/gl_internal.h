@@ -235,13 +235,14 @@ void launch_update(const Problem &pb, const double *u, const double *base, doubl
                    float *Hk, double *S_out, const double *partial, int nsplit, hipStream_t s);
 
 // ---- adjoint
-// One reverse step: mu = r stencil(lam1); A = mu (+ base) + sum_s partial[s];
+// One reverse step: mu = r stencil(lam1); A = mu (+ base) + sum_s partial[s] + sum over
+// rows t = first .. nrows - 1 (stride ld, nullable when nrows = 0) of psi(nrows - t) rows[t];
 // lam0 = lam1 + dt f'(uk) lam1 + A; Mrow = (float) mu; and per-workgroup partial sums
 // of lam1 * Sk, lam1 * Gk, lam1 * df/drate(uk) into grad[3 * blockIdx].
 void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, float *Mrow,
                            const double *partial, int nsplit, const double *base,
-                           const double *uk, const double *Sk, const double *Gk, double *grad,
-                           hipStream_t s);
+                           const float *rows, int nrows, int first, const double *uk,
+                           const double *Sk, const double *Gk, double *grad, hipStream_t s);
 // Workgroups of one adjoint update launch for P points.
 int adjoint_groups(int64_t P);
 // dparams[0..2] = {dL/dalpha, dL/dgamma, dL/drate} from the per-step partial sums
