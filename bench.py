@@ -34,6 +34,12 @@ BF16_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix, TFLOP/s
 PREFIX_MACS = 4.72e10   # oracle sample: the first steps of the workload, about this many MACs
 
 
+def default_block(P):
+    """The library's block length for block_B = 0 (gl_problem docs): 512 rows from 131072
+    points, else 256."""
+    return 512 if P >= 131072 else 256
+
+
 def grid_of(p):
     return [p["nx"], p["ny"]] + ([p["nz"]] if p["ndim"] == 3 else [])
 
@@ -286,7 +292,7 @@ def run_path(path, w, steps, warmup, block_B, prefix=True, nsteps=None):
     P = gl.npoints(p)
     u0 = torch.as_tensor(w["u0"], dtype=torch.float64).cuda()
     s = gl.Solver(p, w["memory"], u0, max_steps=n, sum_path=path, block_B=block_B)
-    B = block_B or 256
+    B = block_B or default_block(P)
     terms = [s.schedule_terms(k) for k in range(n)]
     macs = P * sum(terms)
     work = algorithmic_work(path, P, n, B, terms, p["ndim"])
@@ -609,10 +615,12 @@ def main():
         w = W.cfg2()
         n = args.profile_steps or w["nsteps"]
         for path in [x for x in args.paths.split(",") if x]:
-            work = algorithmic_work(path, W.npoints(w["problem"]), n, args.block_B or 256,
+            work = algorithmic_work(path, W.npoints(w["problem"]), n,
+                                    args.block_B or default_block(W.npoints(w["problem"])),
                                     [k + 1 for k in range(n)])
             print("\n".join(summarize_counters(*args.summarize_counters, work,
-                                                args.block_B or 256)))
+                                                args.block_B or
+                                                default_block(W.npoints(w["problem"])))))
         return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the solver runs on a single "

@@ -112,7 +112,8 @@ typedef struct gl_options {
     int64_t short_L;    /* short-memory window in steps, >= 0 */
     int32_t adapt_a;    /* adaptive base interval [0, a], a >= 2 */
     int32_t sum_path;   /* GL_SUM_* */
-    int32_t block_B;    /* Toeplitz block length: 0 (default 256) or 32, 64, 128, 256, 512 */
+    int32_t block_B;    /* Toeplitz block length: 32, 64, 128, 256, 512, or 0: 512 when the
+                           largest problem has >= 131072 points, else 256 */
     int32_t check_finite; /* nonzero: gl_step_n fails with GL_ENONFINITE on NaN/Inf state */
     int64_t max_steps;  /* history capacity in steps, >= 1 */
     int64_t ckpt_every; /* adjoint: recompute segment length C (0 = default 500) */

@@ -77,6 +77,7 @@ namespace {
 thread_local std::string g_thread_err;
 
 constexpr int64_t kMaxPoints = int64_t(1) << 28;  // per problem
+constexpr int64_t kLargeGrid = 131072;  // points from which the default block length is 512
 
 gl_status load_initial(gl_ctx *ctx, const double *u0);
 
@@ -263,7 +264,15 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     const int64_t rows = opt.max_steps + 1;
 
     const bool toep = opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
-    ctx->B = opt.block_B ? opt.block_B : 256;
+    // default block length: 512 rows for large grids, where halving the history reads per
+    // product outweighs the longer sub-block products (measured: 10% faster at 512^2, 1.6%
+    // at 256^2 where the default stays 256), 256 otherwise
+    int64_t largest = 0;
+    for (int32_t i = 0; i < nprob; ++i)
+        largest = std::max<int64_t>(largest, (int64_t)probs[i].nx *
+                                                 (probs[i].ndim >= 2 ? probs[i].ny : 1) *
+                                                 (probs[i].ndim == 3 ? probs[i].nz : 1));
+    ctx->B = opt.block_B ? opt.block_B : (largest >= kLargeGrid ? 512 : 256);
     // a second level of blocking when the sub-block length divides the block length
     ctx->B2 = (ctx->tune.sub_B > 0 && ctx->tune.sub_B < ctx->B && ctx->B % ctx->tune.sub_B == 0)
                   ? (int)ctx->tune.sub_B
