@@ -92,3 +92,21 @@ def test_ensemble_and_adjoint_after_autotune():
         assert rel_l2(du0[off:off + P], du0r) <= 1e-7
         assert np.all(np.abs(dpar[i] - dparr) <= 1e-7 * np.abs(dparr)), (dpar[i], dparr)
         off += P
+
+
+def test_blocked_autotune_on_a_large_3d_grid():
+    # 64 x 64 x 32 = 131072 points: the default block length is 512 rows, whose product
+    # targets half as many workgroups per CU; tuning, state and parity as above
+    p = W.problem(3, 64, 0.7, 1.0, 0.05, rxn="linear", rate=0.2)
+    p["nz"] = 32
+    u0 = W.gaussian(p, 55)
+    n = 1100
+    G = gl()
+    print_case("autotune blocked 3D", W.npoints(p))
+    with G.Solver(p, W.memory("full"), torch.as_tensor(u0), max_steps=n,
+                  sum_path="toeplitz") as s:
+        g, w = s.autotune()
+        assert g in GEMV_TARGETS and w in (1, 2, 4)
+        assert s.k == 0 and np.array_equal(s.state().cpu().numpy(), u0)
+        got = s.step(n).cpu().numpy()
+    assert rel_l2(got, oracle.run(p, W.memory("full"), u0, n)) <= 1e-5
