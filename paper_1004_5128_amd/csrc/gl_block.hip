@@ -178,10 +178,15 @@ __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
     // loads rows) rows cp, cp + 4, ... of k - nr .. k - 1 at its tile point, into slot 0's row
     // registers
     double pn[2];
+    // step pairs past the next launch's n_next steps (3D launches take at most two) have no
+    // carry to form: their waves (cp is uniform per wave) skip the loads and the sums
+    const bool cpair = 2 * cp < a.n_next;
     if (to_carry) {
+        if (cpair) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-            pn[h] = a.pre[(int64_t)(a.pre_row + s + min(2 * cp + h, a.n_next - 1)) * P + cq];
+            for (int h = 0; h < 2; ++h)
+                pn[h] = a.pre[(int64_t)(a.pre_row + s + min(2 * cp + h, a.n_next - 1)) * P + cq];
+        }
         if (from_carry) {
 #pragma unroll
             for (int e = 0; e < kRowBatch / 4; ++e)
@@ -321,7 +326,7 @@ __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
     // being m = nr + s - jj + i steps back from the next launch's step i.
     if (to_carry) {
         __syncthreads();
-        if (cok) {
+        if (cok && cpair) {
             const int m0 = nr + s, i0 = 2 * cp;
             double c[2];
 #pragma unroll
