@@ -76,7 +76,7 @@ __device__ __forceinline__ double step_reaction(int rxn, double rate, double u) 
     return 0.0;
 }
 
-template <int S, bool D3>
+template <int S, bool D3, bool kFromCarry>
 __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
     using G = StepGeom<S, D3>;
     __shared__ double lu[2][G::kULen];
@@ -102,7 +102,9 @@ __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
     const int64_t gz0 = (int64_t)tiz * tz - S * hz;
     const int s = a.s;
     const int64_t k = a.k;
-    const bool from_carry = a.carry_in != nullptr;
+    // compile-time: a launch that starts from a carry never loads the sub-block's rows into
+    // registers, and without them its kernel fits two workgroups per CU
+    constexpr bool from_carry = kFromCarry;
     const bool to_carry = a.carry_out != nullptr;  // the host keeps b2 + s <= kRowBatch then
 
     // u[k] on the u region (zero outside the grid), held in registers until the history
@@ -351,17 +353,17 @@ __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
     }
 }
 
-template <int S>
+template <int S, bool C>
 __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs a) {
-    block_steps_body<S, false>(a);
+    block_steps_body<S, false, C>(a);
 }
 
 // A 3D grid has four times the tiles of a 2D grid of the same size: at most 64 VGPRs
 // (eight waves per SIMD) keep two workgroups of 16 waves resident per CU.
-template <int S>
+template <int S, bool C>
 __global__ __launch_bounds__(kStepThreads) __attribute__((amdgpu_waves_per_eu(8)))
 void block_steps_kernel_3d(BlockStepArgs a) {
-    block_steps_body<S, true>(a);
+    block_steps_body<S, true, C>(a);
 }
 
 void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
@@ -372,20 +374,29 @@ void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
                          : (args.nx + kTile1 - 1) / kTile1;
     const dim3 grid((unsigned)ntiles), block(kStepThreads);
     static_assert(kMaxFuse3 == 2, "3D instantiations");
+    const bool c = args.carry_in != nullptr;
+#define GL_STEP_CASE(kern, S)                                                                  \
+    do {                                                                                       \
+        if (c)                                                                                 \
+            GL_LAUNCH((kern<S, true>), grid, block, 0, s, args);                               \
+        else                                                                                   \
+            GL_LAUNCH((kern<S, false>), grid, block, 0, s, args);                              \
+    } while (0)
     if (args.ndim == 3) {  // s <= kMaxFuse3, checked by the caller
         if (args.s <= 1)
-            GL_LAUNCH(block_steps_kernel_3d<1>, grid, block, 0, s, args);
+            GL_STEP_CASE(block_steps_kernel_3d, 1);
         else
-            GL_LAUNCH(block_steps_kernel_3d<2>, grid, block, 0, s, args);
+            GL_STEP_CASE(block_steps_kernel_3d, 2);
     } else if (args.s <= 1) {
-        GL_LAUNCH(block_steps_kernel<1>, grid, block, 0, s, args);
+        GL_STEP_CASE(block_steps_kernel, 1);
     } else if (args.s <= 2) {
-        GL_LAUNCH(block_steps_kernel<2>, grid, block, 0, s, args);
+        GL_STEP_CASE(block_steps_kernel, 2);
     } else if (args.s <= 4) {
-        GL_LAUNCH(block_steps_kernel<4>, grid, block, 0, s, args);
+        GL_STEP_CASE(block_steps_kernel, 4);
     } else {
-        GL_LAUNCH(block_steps_kernel<8>, grid, block, 0, s, args);
+        GL_STEP_CASE(block_steps_kernel, 8);
     }
+#undef GL_STEP_CASE
 }
 
 }  // namespace gl
