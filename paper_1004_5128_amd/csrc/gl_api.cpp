@@ -622,6 +622,10 @@ gl_status toeplitz_steps(gl_ctx *ctx, gl::Problem &pb, int64_t k, int64_t s,
         if (pb.carry_k == k && s <= pb.carry_n) {
             args.carry_in = pb.carry[pb.carry_cur];
             out_buf = pb.carry_cur ^ 1;
+        } else if (b2 == 0 && args.has_pre) {
+            // a sub-block's first launch has no rows of its own to sum: its chains start at
+            // Old + Old2, which the carry variant of the kernel reads as its carry
+            args.carry_in = args.pre + (int64_t)args.pre_row * pb.P;
         }
         if (b2 + s < sub_len) {
             args.carry_out = pb.carry[out_buf];
