@@ -949,7 +949,9 @@ gl_status time_best(gl_ctx *ctx, int reps, F launch, float *best) {
 // the run overwrites before reading them, so the context stays at step 0.
 gl_status autotune_impl(gl_ctx *ctx, int32_t what, int64_t *chosen) {
     const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
-    const int64_t kmid = std::max<int64_t>(1, ctx->opt.max_steps / 2);
+    // a step the run can take (k <= max_steps - 1), so the rows and checkpoint slots the
+    // candidates write exist
+    const int64_t kmid = ctx->opt.max_steps / 2;
     const int nprob = (int)ctx->probs.size();
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     const bool prof = ctx->prof;

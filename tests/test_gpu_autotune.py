@@ -110,3 +110,17 @@ def test_blocked_autotune_on_a_large_3d_grid():
         assert s.k == 0 and np.array_equal(s.state().cpu().numpy(), u0)
         got = s.step(n).cpu().numpy()
     assert rel_l2(got, oracle.run(p, W.memory("full"), u0, n)) <= 1e-5
+
+
+@pytest.mark.parametrize("path", ["gemv", "toeplitz"])
+def test_autotune_on_a_one_step_context(path):
+    # the candidates run at step max_steps / 2 = 0: one history row and checkpoints every
+    # step; the context then takes its one step and matches the oracle
+    p = W.problem(2, 12, 0.7, 1.0, 0.1)
+    u0 = W.gaussian(p, 56)
+    G = gl()
+    with G.Solver(p, W.memory("full"), torch.as_tensor(u0), max_steps=1, ckpt_every=1,
+                  sum_path=path) as s:
+        s.autotune()
+        got = s.step(1).cpu().numpy()
+    assert rel_l2(got, oracle.run(p, W.memory("full"), u0, 1)) <= 1e-12
