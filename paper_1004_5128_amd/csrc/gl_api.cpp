@@ -23,7 +23,7 @@ struct gl_ctx {
     int64_t total_points = 0;  // sum of problem points
     gl::Schedule sched;
     gl::Run *d_runs = nullptr;
-    double *partial = nullptr;  // kMaxSplits x max P (FP64)
+    double *partial = nullptr;  // GEMV partial sums of one problem: its most splits x P (FP64)
     int *d_flag = nullptr;
     float *tpart = nullptr;  // Toeplitz product chunks: max chunks x B x P (FP32)
     int64_t tpart_len = 0;   // its length in floats
@@ -78,6 +78,14 @@ thread_local std::string g_thread_err;
 
 constexpr int64_t kMaxPoints = int64_t(1) << 28;  // per problem
 constexpr int64_t kLargeGrid = 131072;  // points from which the default block length is 512
+constexpr int64_t kMaxGemvTarget = 4096;  // largest GEMV workgroup target gl_autotune tries
+
+// Most splits the GEMV can cut P points into for a workgroup target (gemv_splits's bound
+// without the term count): enough splits to reach the target over the column blocks.
+int64_t split_bound(int64_t P, int64_t target) {
+    const int64_t colblocks = (P + gl::kGemvCols - 1) / gl::kGemvCols;
+    return std::min<int64_t>(gl::kMaxSplits, std::max<int64_t>(1, (target + colblocks - 1) / colblocks));
+}
 
 gl_status load_initial(gl_ctx *ctx, const double *u0);
 
@@ -310,7 +318,16 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     ctx->C = opt.ckpt_every > 0 ? opt.ckpt_every : 500;
     const int64_t nsnap = opt.max_steps / ctx->C + 1;
     for (const gl::Problem &pb : ctx->probs) need += (size_t)nsnap * pb.P * sizeof(double);
-    need += 2 * (size_t)gl::kMaxSplits * ctx->total_points * sizeof(double);  // partials (bound)
+    // GEMV partial sums: the most splits any workgroup target up to the largest candidate can
+    // give each problem (a large grid fills the GPU with column blocks alone and needs one)
+    const int64_t tmax = std::max<int64_t>(kMaxGemvTarget, ctx->tune.gemv_groups);
+    size_t bpart_cap = 0, part_len = 0;
+    for (const gl::Problem &pb : ctx->probs) {
+        const int64_t share = (tmax * pb.P + ctx->total_points - 1) / ctx->total_points;
+        bpart_cap += (size_t)split_bound(pb.P, share) * pb.P;
+        part_len = std::max(part_len, (size_t)split_bound(pb.P, tmax) * pb.P);
+    }
+    need += (bpart_cap + part_len) * sizeof(double);
     // FP32 chunk products: the largest chunks x B x P over the problems
     // (a sub-block product needs at most ceil(rows / 128) <= B / 128 chunks of B2 <= 128 rows
     // of sums, so a block product's B rows of one chunk cover it)
@@ -330,13 +347,13 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     ctx->sched = gl::build_schedule(opt, opt.max_steps);
     gl_status st;
     // room for every problem's largest split count, whatever GEMV target gl_autotune picks
-    ctx->bpart_cap = (size_t)gl::kMaxSplits * ctx->total_points;
+    ctx->bpart_cap = bpart_cap;
     if ((st = dev_alloc(ctx, &ctx->bpartial, ctx->bpart_cap))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_batch, (size_t)nprob))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_runs, ctx->sched.runs.size()))) return st;
     HIP_TRY(ctx, hipMemcpy(ctx->d_runs, ctx->sched.runs.data(),
                            ctx->sched.runs.size() * sizeof(gl::Run), hipMemcpyHostToDevice));
-    if ((st = dev_alloc(ctx, &ctx->partial, (size_t)gl::kMaxSplits * maxP))) return st;
+    if ((st = dev_alloc(ctx, &ctx->partial, part_len))) return st;
     if ((st = dev_alloc(ctx, &ctx->d_flag, 1))) return st;
 
     if (toep && (st = dev_alloc(ctx, &ctx->tpart, (size_t)std::max<int64_t>(tpart_len, 1))))
@@ -964,7 +981,8 @@ gl_status autotune_impl(gl_ctx *ctx, int32_t what, int64_t *chosen) {
         const int cur = ctx->probs[0].cur;
         float best = 0.f;
         int64_t best_g = ctx->tune.gemv_groups;
-        for (int64_t g : {256, 512, 1024, 2048, 4096}) {
+        for (int64_t g : {int64_t(256), int64_t(512), int64_t(1024), int64_t(2048),
+                          kMaxGemvTarget}) {
             HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
             if ((st = apply_gemv_target(ctx, g)) != GL_OK) break;
             float ms = 0.f;

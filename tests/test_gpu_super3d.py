@@ -267,3 +267,25 @@ def test_blocked_path_error_paths():
         with pytest.raises(G.GLError) as e:
             s.step(40)
         assert e.value.status == G.GL_ENONFINITE
+
+
+def test_largest_grid():
+    # 1024 x 512 x 512 = 2^28 points, the most a problem may hold (the kernels address points
+    # with 32-bit byte offsets): two plain-path steps match the oracle; one more point is
+    # refused; the blocked path's default 512-row block sums (1 TB) are refused as GL_ENOMEM
+    G = gl()
+    p = box((1024, 512, 512), 0.8, 0.02, rxn="linear", rate=0.1)
+    u0 = W.gaussian(p, 57, noise=0.0)
+    print_case("largest grid", W.npoints(p))
+    got = gpu_run(p, W.memory("full"), u0, 2)
+    ref = oracle.run(p, W.memory("full"), u0, 2)
+    assert rel_l2(got, ref) <= TOL_PLAIN
+    del ref
+    probs = (G.gl_problem * 1)(G.make_problem(dict(p, nz=513)))
+    with pytest.raises(G.GLError) as e:   # refused before u0 is read
+        G.gl_init(probs, 1, G.make_options(W.memory("full"), 2),
+                  torch.zeros(1, dtype=torch.float64, device="cuda"))
+    assert e.value.status == G.GL_EINVAL
+    with pytest.raises(G.GLError) as e:
+        G.Solver(p, W.memory("full"), torch.as_tensor(u0), max_steps=600, sum_path="toeplitz")
+    assert e.value.status == G.GL_ENOMEM
