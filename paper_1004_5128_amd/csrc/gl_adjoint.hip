@@ -12,8 +12,10 @@
 // uses the schedule's transpose instead).  On the blocked path that sum, like
 // the forward one, takes the mu rows before its block of reverse steps as one
 // matrix-core product per block (the Toeplitz kernel over the mu history) and
-// the rows since the block's start by the GEMV; G below is formed the same way
-// with the d psi / d gamma tables over the delta history.  Gradients with dt
+// the rows since by the in-block kernel, several reverse steps per launch (the
+// in-block source holds it); G below is formed per block with the d psi / d gamma
+// tables over the delta history, and the dot products of a segment's steps come
+// from one launch of the dots kernel here.  Gradients with dt
 // and dx fixed, S[k] = sum psi(m) delta[k-m] and G[k] = sum d psi/d gamma (m)
 // delta[k-m]:
 //   dL/dalpha = (r/alpha) sum_k <lam[k+1], S[k]>
@@ -41,14 +43,30 @@ __device__ __forceinline__ double adj_dfdrate(int rxn, double u) {
     return 0.0;
 }
 
+// Fixed-tree sum of the three per-lane terms over the workgroup into grad[0..2].
+__device__ __forceinline__ void adj_group_sums(double t0, double t1, double t2,
+                                               double *__restrict__ grad) {
+    __shared__ double red[3][kAdjThreads];
+    red[0][threadIdx.x] = t0;
+    red[1][threadIdx.x] = t1;
+    red[2][threadIdx.x] = t2;
+    __syncthreads();
+    for (int h = kAdjThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + h];
+            red[1][threadIdx.x] += red[1][threadIdx.x + h];
+            red[2][threadIdx.x] += red[2][threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) grad[threadIdx.x] = red[threadIdx.x][0];
+}
+
 __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
     const double *__restrict__ lam1, double *__restrict__ lam0, float *__restrict__ Mrow,
-    const double *__restrict__ partial, int nsplit, const double *__restrict__ base,
-    const float *__restrict__ rows, int64_t ld, int nrows, int first,
-    const double *__restrict__ psi, int64_t P, int ndim, int nx, int ny, int nz,
+    const double *__restrict__ partial, int nsplit, int64_t P, int ndim, int nx, int ny, int nz,
     double r, double dt, int rxn, double rate, const double *__restrict__ uk,
     const double *__restrict__ Sk, const double *__restrict__ Gk, double *__restrict__ grad) {
-    __shared__ double red[3][kAdjThreads];
     const int64_t p = (int64_t)blockIdx.x * kAdjThreads + threadIdx.x;
     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
     if (p < P) {
@@ -77,7 +95,6 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
         }
         const double mu = r * lap;
         double A = mu;
-        if (base) A += base[p];
         int q = 0;
         for (; q + 8 <= nsplit; q += 8) {
             double v[8];
@@ -87,15 +104,6 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
             for (int i = 0; i < 8; ++i) A += v[i];
         }
         for (; q < nsplit; ++q) A += partial[(int64_t)q * P + p];
-        // the mu rows since the sub-block's start, row t at offset nrows - t, ascending t
-        for (int t = first; t < nrows; t += 8) {
-            float v[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = rows[(int64_t)min(t + e, nrows - 1) * ld + p];
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if (t + e < nrows) A = fma(psi[nrows - t - e], (double)v[e], A);
-        }
         const double l1 = lam1[p];
         const double u = uk[p];
         lam0[p] = l1 + dt * adj_dfdu(rxn, rate, u) * l1 + A;
@@ -104,31 +112,47 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_update_kernel(
         t1 = l1 * Gk[p];
         t2 = l1 * adj_dfdrate(rxn, u);
     }
-    red[0][threadIdx.x] = t0;
-    red[1][threadIdx.x] = t1;
-    red[2][threadIdx.x] = t2;
-    __syncthreads();
-    for (int h = kAdjThreads / 2; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + h];
-            red[1][threadIdx.x] += red[1][threadIdx.x + h];
-            red[2][threadIdx.x] += red[2][threadIdx.x + h];
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x < 3) grad[(int64_t)blockIdx.x * 3 + threadIdx.x] = red[threadIdx.x][0];
+    adj_group_sums(t0, t1, t2, grad + (int64_t)blockIdx.x * 3);
 }
 
 int adjoint_groups(int64_t P) { return (int)((P + kAdjThreads - 1) / kAdjThreads); }
 
 void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, float *Mrow,
-                           const double *partial, int nsplit, const double *base,
-                           const float *rows, int nrows, int first, const double *uk,
-                           const double *Sk, const double *Gk, double *grad, hipStream_t s) {
+                           const double *partial, int nsplit, const double *uk, const double *Sk,
+                           const double *Gk, double *grad, hipStream_t s) {
     const gl_problem &p = pb.p;
     GL_LAUNCH(adjoint_update_kernel, dim3((unsigned)adjoint_groups(pb.P)), dim3(kAdjThreads), 0, s,
-              lam1, lam0, Mrow, partial, nsplit, base, rows, pb.ld, nrows, first, pb.psi, pb.P,
-              p.ndim, p.nx, p.ny, p.nz, pb.r, p.dt, p.rxn, p.rxn_rate, uk, Sk, Gk, grad);
+              lam1, lam0, Mrow, partial, nsplit, pb.P, p.ndim, p.nx, p.ny, p.nz, pb.r, p.dt,
+              p.rxn, p.rxn_rate, uk, Sk, Gk, grad);
+}
+
+// blockIdx.x: group of 256 points; steps j = blockIdx.y, blockIdx.y + gridDim.y, .. < nk.
+// The terms and their tree are the update kernel's, so both paths give the same sums for the
+// same lam, u, S and G.
+__global__ __launch_bounds__(kAdjThreads) void adjoint_dots_kernel(
+    const double *__restrict__ lam, const double *__restrict__ u, const double *__restrict__ S,
+    const double *__restrict__ G, int64_t P, int rxn, int64_t k_lo, int64_t nk,
+    double *__restrict__ grad) {
+    const int64_t p = (int64_t)blockIdx.x * kAdjThreads + threadIdx.x;
+    for (int64_t j = blockIdx.y; j < nk; j += gridDim.y) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+        if (p < P) {
+            const double l1 = lam[(j + 1) * P + p];
+            t0 = l1 * S[j * P + p];
+            t1 = l1 * G[j * P + p];
+            t2 = l1 * adj_dfdrate(rxn, u[j * P + p]);
+        }
+        adj_group_sums(t0, t1, t2, grad + ((k_lo + j) * gridDim.x + blockIdx.x) * 3);
+        __syncthreads();  // the next step's sums reuse the reduction array
+    }
+}
+
+void launch_adjoint_dots(const Problem &pb, const double *lam, const double *u, const double *S,
+                         const double *G, int64_t k_lo, int64_t nk, double *grad, hipStream_t s) {
+    if (nk <= 0) return;
+    const dim3 grid((unsigned)adjoint_groups(pb.P), (unsigned)std::min<int64_t>(nk, 65535));
+    GL_LAUNCH(adjoint_dots_kernel, grid, dim3(kAdjThreads), 0, s, lam, u, S, G, pb.P, pb.p.rxn,
+              k_lo, nk, grad);
 }
 
 // One workgroup: lane t sums entries t, t + 256, ... in order, then a fixed tree.

@@ -39,17 +39,17 @@ struct gl_ctx {
     double *adj_u = nullptr;     // recomputed states of one segment, (C + 1) x max P
     double *adj_S = nullptr;     // the forward sums S[k] of one segment, C x max P
     double *adj_G = nullptr;     // the sums with d psi / d gamma, C x max P
-    double *adj_lam[2] = {nullptr, nullptr};
+    double *adj_lam[2] = {nullptr, nullptr};  // plain path: lam[k + 1] and lam[k]
+    double *adj_lamseg = nullptr;  // blocked path: lam[ks .. ke] of a segment, (C + 1) x max P
     double *adj_grad = nullptr;  // per step and workgroup partial dot products, 3 each
     gl::Run *adj_runs = nullptr;  // adaptive memory: the transposed schedule's runs
     size_t adj_runs_cap = 0;
     // blocked adjoint (Toeplitz path): the sums over the mu rows before a block of reverse
-    // steps (psi), the sums G of a block's steps over the delta history (d psi / d gamma), and
-    // the run lists m = 0 .. min(c, L) for the mu rows after a block's start
+    // steps (psi) and before a sub-block, and the sums G of a block's steps over the delta
+    // history (d psi / d gamma)
     double *adj_oldA = nullptr, *adj_oldG = nullptr;  // B x max P each
     double *adj_oldA2 = nullptr;                       // B2 x max P (sub-block sums)
     int64_t adj_oldA_r0 = -1, adj_oldA2_r1 = -1;
-    gl::Run *adj_recent = nullptr;                     // B entries
     int64_t maxP = 0, maxld = 0;
     int B = 256;             // block length of the Toeplitz path
     int B2 = 0;              // sub-block length inside a block (0: one level)
@@ -683,11 +683,6 @@ gl_status step_toeplitz(gl_ctx *ctx, int64_t limit, int64_t *done) {
 // Recomputes u[ks..ke] of one problem from the snapshot u[ks] with the forward's own
 // kernels (bit-identical to the forward run), keeping u[k] in adj_u, the step sums S[k]
 // in adj_S and the sums G[k] with d psi / d gamma in adj_G (k in [ks, ke)).
-// Terms (m = 0 included) of the run adj_recent[c]: offsets 0 .. min(c, L).
-int64_t recent_terms(const gl_ctx *ctx, int64_t c) {
-    return (ctx->opt.mem_mode == GL_MEM_SHORT ? std::min<int64_t>(c, ctx->opt.short_L) : c) + 1;
-}
-
 gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke) {
     const int64_t P = pb.P;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_u, pb.snap + (ks / ctx->C) * P, P * sizeof(double),
@@ -756,7 +751,7 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
                   ((size_t)(3 * C + 1) * ctx->maxP + 2 * (size_t)ctx->maxP +
                    (size_t)n * groups * 3) * sizeof(double);
     if (toep) {
-        need += (2 * (size_t)ctx->B + ctx->B2) * ctx->maxP * sizeof(double);
+        need += (2 * (size_t)ctx->B + ctx->B2 + C + 1) * ctx->maxP * sizeof(double);
         for (const gl::Problem &pb : ctx->probs) need += 16 * (size_t)pb.tab_len * sizeof(uint16_t);
     }
     size_t free_b = 0, total_b = 0;
@@ -777,16 +772,7 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
         if ((st = dev_alloc(ctx, &ctx->adj_oldG, (size_t)ctx->B * ctx->maxP))) return st;
         if (ctx->B2 && (st = dev_alloc(ctx, &ctx->adj_oldA2, (size_t)ctx->B2 * ctx->maxP)))
             return st;
-        // run c: offsets m = 0 .. min(c, L) (the sums skip m = 0, added by the update)
-        std::vector<gl::Run> recent(ctx->B);
-        for (int c = 0; c < ctx->B; ++c) {
-            int64_t cnt = c;
-            if (ctx->opt.mem_mode == GL_MEM_SHORT) cnt = std::min<int64_t>(cnt, ctx->opt.short_L);
-            recent[c] = gl::Run{0, (int32_t)cnt + 1, 1, 1};
-        }
-        if ((st = dev_alloc(ctx, &ctx->adj_recent, recent.size()))) return st;
-        HIP_TRY(ctx, hipMemcpy(ctx->adj_recent, recent.data(), recent.size() * sizeof(gl::Run),
-                               hipMemcpyHostToDevice));
+        if ((st = dev_alloc(ctx, &ctx->adj_lamseg, (size_t)(C + 1) * ctx->maxP))) return st;
         // d psi / d gamma tables (zero past a short-memory window, as the psi tables)
         const int64_t npsi = ctx->opt.max_steps + gl::kMaxBlock + 1;
         const int64_t nkeep = ctx->opt.mem_mode == GL_MEM_SHORT
@@ -829,6 +815,68 @@ gl_status reverse_schedule(gl_ctx *ctx, int64_t n, gl::Schedule *tsched,
     return GL_OK;
 }
 
+// Reverse steps of one segment [ks, ke) of a problem on the blocked path, from lam[ke] in
+// adj_lamseg row ke - ks: the sums over the mu rows before each reverse block by the
+// matrix-core product (once per block), with sub-blocks those over the block's rows before
+// each sub-block by a second product on that base (once per sub-block), and the rows since
+// by the in-block kernel, up to the fusion length of reverse steps per launch inside one
+// sub-block; then the segment's dot products in one launch.
+gl_status adjoint_segment_blocked(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke) {
+    const int64_t n = ctx->k, P = pb.P;
+    const int64_t sub_len = ctx->B2 ? ctx->B2 : ctx->B;
+    const int64_t max_s = pb.p.ndim == 3 ? std::min<int64_t>(ctx->tune.fuse, gl::kMaxFuse3)
+                                         : ctx->tune.fuse;
+    gl_status st;
+    for (int64_t k = ke - 1; k >= ks;) {
+        const int64_t rho = n - 1 - k;  // reverse step
+        const int64_t r0 = rho - rho % ctx->B;
+        if (ctx->adj_oldA_r0 != r0) {
+            if ((st = block_sums(ctx, pb, pb.psi_tab, ctx->adj_M, pb.ld, ctx->B, r0,
+                                 window_lo(ctx, r0), r0, ctx->adj_oldA, nullptr,
+                                 GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE)) != GL_OK)
+                return st;
+            ctx->adj_oldA_r0 = r0;
+            ctx->adj_oldA2_r1 = -1;
+        }
+        const int64_t r1 = rho - rho % sub_len, c = rho - r1;
+        if (r1 > r0 && ctx->adj_oldA2_r1 != r1) {
+            if ((st = block_sums(ctx, pb, pb.psi_tab, ctx->adj_M, pb.ld, ctx->B2, r1,
+                                 std::max(r0, window_lo(ctx, r1)), r1, ctx->adj_oldA2,
+                                 ctx->adj_oldA + (r1 - r0) * P, GL_KERNEL_SUBBLOCK,
+                                 GL_KERNEL_SUB_REDUCE)) != GL_OK)
+                return st;
+            ctx->adj_oldA2_r1 = r1;
+        }
+        const int64_t s = std::max<int64_t>(1, std::min({max_s, sub_len - c, k - ks + 1}));
+        gl::AdjStepArgs args{};
+        args.psi = pb.psi_blk;
+        args.M = ctx->adj_M;
+        args.ld = pb.ld;
+        args.P = P;
+        args.ndim = pb.p.ndim;
+        args.nx = pb.p.nx;
+        args.ny = pb.p.ny;
+        args.nz = pb.p.nz;
+        args.rxn = pb.p.rxn;
+        args.r = pb.r;
+        args.dt = pb.p.dt;
+        args.rate = pb.p.rxn_rate;
+        args.base = (r1 > r0 ? ctx->adj_oldA2 : ctx->adj_oldA) + c * P;
+        args.lam_in = ctx->adj_lamseg + (k + 1 - ks) * P;
+        args.lam_out = ctx->adj_lamseg + (k - ks) * P;
+        args.u = ctx->adj_u + (k - ks) * P;
+        args.rho = rho;
+        args.c = (int32_t)c;
+        args.s = (int32_t)s;
+        gl::launch_adjoint_steps(args, ctx->stream);
+        k -= s;
+    }
+    gl::launch_adjoint_dots(pb, ctx->adj_lamseg, ctx->adj_u, ctx->adj_S, ctx->adj_G, ks, ke - ks,
+                            ctx->adj_grad, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return GL_OK;
+}
+
 // Reverse sweep of every problem over the steps taken so far (see gl_adjoint.hip).
 gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double *dparams) {
     gl_status st;
@@ -843,76 +891,43 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
         gl::Problem &pb = ctx->probs[ip];
         const int64_t P = pb.P;
         const int groups = gl::adjoint_groups(P);
+        const double *lam_top = dL_duT + pb.offset;  // lam at the top of the next segment
         int cur = 0;
         ctx->adj_oldA_r0 = ctx->adj_oldA2_r1 = -1;  // block sums of this problem's mu history
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_lam[0], dL_duT + pb.offset, P * sizeof(double),
-                                    hipMemcpyDeviceToDevice, ctx->stream));
+        if (!toep)
+            HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_lam[0], lam_top, P * sizeof(double),
+                                        hipMemcpyDeviceToDevice, ctx->stream));
         for (int64_t seg = (n - 1) / C; seg >= 0; --seg) {
             const int64_t ks = seg * C, ke = std::min(ks + C, n);
             if ((st = adjoint_recompute(ctx, pb, ks, ke)) != GL_OK) return st;
+            if (toep) {
+                HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_lamseg + (ke - ks) * P, lam_top,
+                                            P * sizeof(double), hipMemcpyDeviceToDevice,
+                                            ctx->stream));
+                if ((st = adjoint_segment_blocked(ctx, pb, ks, ke)) != GL_OK) return st;
+                lam_top = ctx->adj_lamseg;  // lam[ks], row 0
+                continue;
+            }
             for (int64_t k = ke - 1; k >= ks; --k) {
                 const int64_t rho = n - 1 - k;  // reverse step: the reverse schedule at rho
-                const double *base = nullptr;
-                int64_t rb = ts->run_begin[rho], T = ts->terms[rho];
-                int nruns = (int)(ts->run_begin[rho + 1] - rb);
-                const gl::Run *runs = truns + rb;
-                const float *rows = nullptr;
-                int nrows = 0, first = 0;
-                if (toep) {
-                    // blocked, as the forward in reverse time: the mu rows before rho's block by
-                    // the matrix-core product (once per block); with sub-blocks, the block's
-                    // rows before rho's sub-block by a second product on that base (once per
-                    // sub-block) and the <= B2 - 1 rows since summed by the update itself;
-                    // without, the rows since the block's start by the GEMV
-                    const int64_t r0 = rho - rho % ctx->B;
-                    if (ctx->adj_oldA_r0 != r0) {
-                        if ((st = block_sums(ctx, pb, pb.psi_tab, ctx->adj_M, pb.ld, ctx->B, r0,
-                                             window_lo(ctx, r0), r0, ctx->adj_oldA, nullptr,
-                                             GL_KERNEL_TOEPLITZ, GL_KERNEL_OLD_REDUCE)) != GL_OK)
-                            return st;
-                        ctx->adj_oldA_r0 = r0;
-                        ctx->adj_oldA2_r1 = -1;
-                    }
-                    if (ctx->B2) {
-                        const int64_t r1 = rho - rho % ctx->B2, c = rho - r1;
-                        if (r1 > r0 && ctx->adj_oldA2_r1 != r1) {
-                            if ((st = block_sums(ctx, pb, pb.psi_tab, ctx->adj_M, pb.ld, ctx->B2,
-                                                 r1, std::max(r0, window_lo(ctx, r1)), r1,
-                                                 ctx->adj_oldA2, ctx->adj_oldA + (r1 - r0) * P,
-                                                 GL_KERNEL_SUBBLOCK, GL_KERNEL_SUB_REDUCE)) != GL_OK)
-                                return st;
-                            ctx->adj_oldA2_r1 = r1;
-                        }
-                        base = (r1 > r0 ? ctx->adj_oldA2 : ctx->adj_oldA) + c * P;
-                        rows = ctx->adj_M + r1 * pb.ld;
-                        nrows = (int)c;
-                        if (ctx->opt.mem_mode == GL_MEM_SHORT)
-                            first = (int)std::max<int64_t>(0, c - ctx->opt.short_L);
-                        T = 1;  // no GEMV terms
-                    } else {
-                        const int64_t c = rho - r0;
-                        base = ctx->adj_oldA + c * P;
-                        runs = ctx->adj_recent + c;
-                        nruns = 1;
-                        T = recent_terms(ctx, c);
-                    }
-                }
+                const int64_t rb = ts->run_begin[rho], T = ts->terms[rho];
+                const int nruns = (int)(ts->run_begin[rho + 1] - rb);
                 const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
                 if (nsplit > 0)
-                    gl::launch_hist_gemv(ctx->adj_M, pb.ld, P, pb.psi, runs, nruns, rho, 1, T,
-                                         nsplit, false, ctx->partial, ctx->stream);
+                    gl::launch_hist_gemv(ctx->adj_M, pb.ld, P, pb.psi, truns + rb, nruns, rho, 1,
+                                         T, nsplit, false, ctx->partial, ctx->stream);
                 const int64_t i = k - ks;
                 gl::launch_adjoint_update(pb, ctx->adj_lam[cur], ctx->adj_lam[cur ^ 1],
-                                          ctx->adj_M + rho * pb.ld, ctx->partial, nsplit, base,
-                                          rows, nrows, first, ctx->adj_u + i * P,
-                                          ctx->adj_S + i * P, ctx->adj_G + i * P,
-                                          ctx->adj_grad + k * groups * 3, ctx->stream);
+                                          ctx->adj_M + rho * pb.ld, ctx->partial, nsplit,
+                                          ctx->adj_u + i * P, ctx->adj_S + i * P,
+                                          ctx->adj_G + i * P, ctx->adj_grad + k * groups * 3,
+                                          ctx->stream);
                 cur ^= 1;
             }
             HIP_TRY(ctx, hipGetLastError());
         }
-        HIP_TRY(ctx, hipMemcpyAsync(dL_du0 + pb.offset, ctx->adj_lam[cur], P * sizeof(double),
-                                    hipMemcpyDeviceToDevice, ctx->stream));
+        HIP_TRY(ctx, hipMemcpyAsync(dL_du0 + pb.offset, toep ? lam_top : ctx->adj_lam[cur],
+                                    P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         gl::launch_adjoint_final(ctx->adj_grad, n * groups, pb.r, pb.p.alpha, std::log(pb.p.dt),
                                  pb.p.dt, dparams + 3 * ip, ctx->stream);
         HIP_TRY(ctx, hipGetLastError());

@@ -366,13 +366,210 @@ void block_steps_kernel_3d(BlockStepArgs a) {
     block_steps_body<S, true, C>(a);
 }
 
+// ---- reverse steps (adjoint) on the same tiles
+//
+// lam[k] = lam[k+1] + dt f'(u[k]) lam[k+1] + sum_{m >= 0} psi(m) mu[k+m], mu[k] = r Lap lam[k+1]:
+// in reverse time rho = n - 1 - k the mu rows are a history like the forward's delta rows, so
+// reverse step rho + i of a launch takes the forward's in-block chain (the base row, then the
+// sub-block's mu rows in ascending order, the launch's own rows from registers, mu itself
+// last) and the halo scheme above, with lam in place of u.  u[k - i] enters through f'
+// only, read at each point from the segment's recomputed states.
+__device__ __forceinline__ double adj_reaction_slope(int rxn, double rate, double u) {
+    if (rxn == GL_RXN_LINEAR) return -rate;
+    if (rxn == GL_RXN_FISHER) return rate * (1.0 - 2.0 * u);
+    return 0.0;
+}
+
+template <int S, bool D3>
+__device__ __forceinline__ void adjoint_steps_body(const AdjStepArgs &a) {
+    using G = StepGeom<S, D3>;
+    __shared__ double ll[2][G::kULen];
+    const int tid = threadIdx.x;
+    const bool two = !D3 && a.ndim == 2;
+    const int tx = D3 ? kTile3x : two ? kTile2 : kTile1;
+    const int ty = D3 ? kTile3y : two ? kTile2 : 1, tz = D3 ? kTile3z : 1;
+    const int hy = D3 || two ? 1 : 0;
+    constexpr int hz = D3 ? 1 : 0;
+    const int uw = tx + 2 * S, uh = ty + 2 * S * hy, ud = tz + 2 * S * hz;
+    const int w0 = tx + 2 * (S - 1), h0 = ty + 2 * (S - 1) * hy;
+    const int d0 = tz + 2 * (S - 1) * hz;
+    const int uwh = uw * uh, w0h0 = w0 * h0;
+    const int64_t nx = a.nx, ny = hy ? a.ny : 1, nz = D3 ? a.nz : 1, P = a.P;
+    const int ntx = (int)((nx + tx - 1) / tx), nty = (int)((ny + ty - 1) / ty);
+    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int tix = tile % ntx, trest = tile / ntx;
+    const int tiy = D3 ? trest % nty : trest, tiz = D3 ? trest / nty : 0;
+    const int64_t gx0 = (int64_t)tix * tx - S;
+    const int64_t gy0 = (int64_t)tiy * ty - S * hy;
+    const int64_t gz0 = (int64_t)tiz * tz - S * hz;
+    const int s = a.s;
+
+    // lam[k + 1] on the region widened by S (zero outside the grid)
+    constexpr int kULoads = (G::kULen + kStepThreads - 1) / kStepThreads;
+    double lv[kULoads];
+    bool lin[kULoads];
+#pragma unroll
+    for (int c = 0; c < kULoads; ++c) {
+        const int idx = tid + c * kStepThreads;
+        const int iz = D3 ? idx / uwh : 0, ixy = idx - iz * uwh;
+        const int64_t gx = gx0 + ixy % uw, gy = gy0 + ixy / uw, gz = gz0 + iz;
+        lin[c] = idx < uwh * ud && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 &&
+                 gz < nz;
+        lv[c] = a.lam_in[lin[c] ? (gz * ny + gy) * nx + gx : 0];
+    }
+
+    int ux[G::kPts], lvl[G::kPts];
+    int64_t q[G::kPts];
+#pragma unroll
+    for (int n = 0; n < G::kPts; ++n) {
+        const int r = tid + n * kStepThreads;
+        const int rz = D3 ? r / w0h0 : 0, rxy = r - rz * w0h0;
+        const int rx = rxy % w0, ry = rxy / w0;
+        const int64_t gx = gx0 + rx + 1, gy = gy0 + ry + hy, gz = gz0 + rz + hz;
+        const bool ok = r < w0h0 * d0 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 &&
+                        gz < nz;
+        int l = min(rx, w0 - 1 - rx);
+        if (hy) l = min(l, min(ry, h0 - 1 - ry));
+        if (D3) l = min(l, min(rz, d0 - 1 - rz));
+        lvl[n] = ok ? l : -1;
+        ux[n] = ((rz + hz) * uh + ry + hy) * uw + rx + 1;
+        q[n] = ok ? (gz * ny + gy) * nx + gx : 0;
+    }
+
+    // chain starts (base rows), the states u[k - i] and the sub-block's mu rows, all issued
+    // before use; slots without a grid point read point 0, steps past s re-read step s - 1's
+    // rows, rows past the last re-read it (all unused)
+    double acc[G::kPts][S], uk[G::kPts][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        const int ic = min(i, s - 1);
+#pragma unroll
+        for (int n = 0; n < G::kPts; ++n) {
+            acc[n][i] = a.base[(int64_t)ic * P + q[n]];
+            uk[n][i] = a.u[q[n] - (int64_t)ic * P];
+        }
+    }
+    const int nr = a.c;  // rows rho - nr .. rho - 1
+    const float *rows = a.M + (a.rho - nr) * a.ld;
+    for (int j = 0; j < nr; j += kRowBatch) {
+        float v[G::kPts][kRowBatch];
+#pragma unroll
+        for (int t = 0; t < kRowBatch; ++t) {
+            const float *row = rows + (int64_t)min(j + t, nr - 1) * a.ld;
+#pragma unroll
+            for (int n = 0; n < G::kPts; ++n) v[n][t] = row[q[n]];
+        }
+#pragma unroll
+        for (int h = 0; h < kRowBatch / kWin; ++h) {
+            const int j0 = j + h * kWin;
+            if (j0 >= nr) continue;
+            // row j0 + t is m = nr - j0 - t + i steps back from reverse step rho + i
+            double w[kWin + S - 1];
+#pragma unroll
+            for (int x = 0; x < kWin + S - 1; ++x) w[x] = a.psi[max(nr - j0 - (kWin - 1) + x, 0)];
+#pragma unroll
+            for (int t = 0; t < kWin; ++t) {
+                if (j0 + t < nr) {
+#pragma unroll
+                    for (int i = 0; i < S; ++i) {
+                        if (i < s) {
+#pragma unroll
+                            for (int n = 0; n < G::kPts; ++n)
+                                acc[n][i] = fma(w[kWin - 1 - t + i], (double)v[n][h * kWin + t],
+                                                acc[n][i]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    double wl[S];  // psi(1 .. S-1) for the launch's own rows
+#pragma unroll
+    for (int m = 1; m < S; ++m) wl[m] = m < s ? a.psi[m] : 0.0;
+    wl[0] = 0.0;
+
+#pragma unroll
+    for (int c = 0; c < kULoads; ++c) {
+        const int idx = tid + c * kStepThreads;
+        if (idx < uwh * ud) {
+            ll[0][idx] = lin[c] ? lv[c] : 0.0;
+            ll[1][idx] = 0.0;
+        }
+    }
+
+    float ml[G::kPts][S];  // the lane's mu rows rho .. rho + i - 1, FP32 as stored
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+        if (i >= s) break;
+        __syncthreads();  // lam[k - i + 1] complete in ll[i & 1]; its readers of step i - 1 done
+        const double *lc = ll[i & 1];
+        double *ln = ll[(i & 1) ^ 1];
+#pragma unroll
+        for (int n = 0; n < G::kPts; ++n) {
+            if (lvl[n] < i) continue;
+            const int x = ux[n];
+            const double l1 = lc[x];
+            const double lap =
+                D3    ? lc[x + 1] + lc[x - 1] + lc[x + uw] + lc[x - uw] + lc[x + uwh] +
+                            lc[x - uwh] - 6.0 * l1
+                : two ? lc[x + 1] + lc[x - 1] - 4.0 * l1 + lc[x + uw] + lc[x - uw]
+                      : lc[x + 1] - 2.0 * l1 + lc[x - 1];
+            const double mu = a.r * lap;
+            double c = acc[n][i];
+#pragma unroll
+            for (int i2 = 0; i2 < i; ++i2) c = fma(wl[i - i2], (double)ml[n][i2], c);
+            const float mf = (float)mu;
+            ml[n][i] = mf;
+            const double lnew = l1 + a.dt * adj_reaction_slope(a.rxn, a.rate, uk[n][i]) * l1 +
+                                (c + mu);
+            ln[x] = lnew;
+            if (lvl[n] >= S - 1) {  // a point of the tile: results go out
+                a.M[(a.rho + i) * a.ld + q[n]] = mf;
+                a.lam_out[q[n] - (int64_t)i * P] = lnew;
+            }
+        }
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kStepThreads) void adjoint_steps_kernel(AdjStepArgs a) {
+    adjoint_steps_body<S, false>(a);
+}
+
+template <int S>
+__global__ __launch_bounds__(kStepThreads) void adjoint_steps_kernel_3d(AdjStepArgs a) {
+    adjoint_steps_body<S, true>(a);
+}
+
+int64_t step_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz) {
+    return ndim == 3 ? ((nx + kTile3x - 1) / kTile3x) * ((ny + kTile3y - 1) / kTile3y) *
+                           ((nz + kTile3z - 1) / kTile3z)
+           : ndim == 2 ? ((nx + kTile2 - 1) / kTile2) * ((ny + kTile2 - 1) / kTile2)
+                       : (nx + kTile1 - 1) / kTile1;
+}
+
+void launch_adjoint_steps(const AdjStepArgs &args, hipStream_t s) {
+    const dim3 grid((unsigned)step_tiles(args.ndim, args.nx, args.ny, args.nz)),
+        block(kStepThreads);
+    if (args.ndim == 3) {  // s <= kMaxFuse3, checked by the caller
+        if (args.s <= 1)
+            GL_LAUNCH((adjoint_steps_kernel_3d<1>), grid, block, 0, s, args);
+        else
+            GL_LAUNCH((adjoint_steps_kernel_3d<2>), grid, block, 0, s, args);
+    } else if (args.s <= 1) {
+        GL_LAUNCH((adjoint_steps_kernel<1>), grid, block, 0, s, args);
+    } else if (args.s <= 2) {
+        GL_LAUNCH((adjoint_steps_kernel<2>), grid, block, 0, s, args);
+    } else if (args.s <= 4) {
+        GL_LAUNCH((adjoint_steps_kernel<4>), grid, block, 0, s, args);
+    } else {
+        GL_LAUNCH((adjoint_steps_kernel<8>), grid, block, 0, s, args);
+    }
+}
+
 void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
-    const int64_t ntiles =
-        args.ndim == 3   ? ((args.nx + kTile3x - 1) / kTile3x) * ((args.ny + kTile3y - 1) / kTile3y) *
-                             ((args.nz + kTile3z - 1) / kTile3z)
-        : args.ndim == 2 ? ((args.nx + kTile2 - 1) / kTile2) * ((args.ny + kTile2 - 1) / kTile2)
-                         : (args.nx + kTile1 - 1) / kTile1;
-    const dim3 grid((unsigned)ntiles), block(kStepThreads);
+    const dim3 grid((unsigned)step_tiles(args.ndim, args.nx, args.ny, args.nz)),
+        block(kStepThreads);
     static_assert(kMaxFuse3 == 2, "3D instantiations");
     const bool c = args.carry_in != nullptr;
 #define GL_STEP_CASE(kern, S)                                                                  \

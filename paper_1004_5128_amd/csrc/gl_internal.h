@@ -235,14 +235,40 @@ void launch_update(const Problem &pb, const double *u, const double *base, doubl
                    float *Hk, double *S_out, const double *partial, int nsplit, hipStream_t s);
 
 // ---- adjoint
-// One reverse step: mu = r stencil(lam1); A = mu (+ base) + sum_s partial[s] + sum over
-// rows t = first .. nrows - 1 (stride ld, nullable when nrows = 0) of psi(nrows - t) rows[t];
+// One reverse step of the plain path: mu = r stencil(lam1); A = mu + sum_s partial[s];
 // lam0 = lam1 + dt f'(uk) lam1 + A; Mrow = (float) mu; and per-workgroup partial sums
 // of lam1 * Sk, lam1 * Gk, lam1 * df/drate(uk) into grad[3 * blockIdx].
 void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, float *Mrow,
-                           const double *partial, int nsplit, const double *base,
-                           const float *rows, int nrows, int first, const double *uk,
-                           const double *Sk, const double *Gk, double *grad, hipStream_t s);
+                           const double *partial, int nsplit, const double *uk, const double *Sk,
+                           const double *Gk, double *grad, hipStream_t s);
+
+// Reverse steps rho .. rho + s - 1 of one sub-block on the blocked path (forward steps
+// k, k - 1, .. k - s + 1, k = n - 1 - rho), in one launch with the in-block kernel's tiles and
+// halos.  The sum of reverse step rho + i over the mu history runs as the forward's in-block
+// chain: base row i, then psi(m) times the mu rows rho - c .. rho + i - 1 in ascending order,
+// then mu[k - i] itself (psi(0) = 1); the result does not depend on how the steps are grouped.
+struct AdjStepArgs {
+    const double *psi;    // psi, zero past a short-memory window
+    float *M;             // mu history in reverse time (stride ld): reads rows rho - c ..
+                          // rho - 1, writes rows rho .. rho + s - 1
+    int64_t ld, P;
+    int32_t ndim, nx, ny, nz, rxn;
+    double r, dt, rate;
+    const double *base;   // row i (stride P): the sums over the mu rows before rho - c
+    const double *lam_in; // lam[k + 1]
+    double *lam_out;      // lam[k - i] goes to lam_out - i P (the rows descend in memory)
+    const double *u;      // u[k - i] at u - i P
+    int64_t rho;
+    int32_t c;            // mu rows summed from the history (rho - c .. rho - 1)
+    int32_t s;            // 1 .. kMaxFuse (kMaxFuse3 in 3D)
+};
+void launch_adjoint_steps(const AdjStepArgs &args, hipStream_t s);
+
+// Per-workgroup partial sums for the steps k = k_lo .. k_lo + nk - 1 of a segment, as the
+// plain path's update forms them: lam1 * S, lam1 * G, lam1 * df/drate(u) with lam1 row
+// k - k_lo + 1 of lam, S, G and u rows k - k_lo; into grad + 3 (k groups + blockIdx).
+void launch_adjoint_dots(const Problem &pb, const double *lam, const double *u, const double *S,
+                         const double *G, int64_t k_lo, int64_t nk, double *grad, hipStream_t s);
 // Workgroups of one adjoint update launch for P points.
 int adjoint_groups(int64_t P);
 // dparams[0..2] = {dL/dalpha, dL/dgamma, dL/drate} from the per-step partial sums
