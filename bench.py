@@ -594,6 +594,8 @@ def main():
                     help="time the block product alone at step K (for counter collection)")
     ap.add_argument("--probe-hipblaslt", action="store_true",
                     help="time vendor BF16 GEMMs (torch.matmul) for comparison")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint leg and print its JSON (for kernel traces)")
     ap.add_argument("--paper-fig3", action="store_true",
                     help="the paper's short vs adaptive memory comparison (Sec. 3.2)")
     args = ap.parse_args()
@@ -626,6 +628,9 @@ def main():
         print("bench.py: this build measures one GPU only (the solver runs on a single "
               "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_128x128_5000steps": run_adjoint_leg()}), flush=True)
+        return
 
     import torch
     from paper_1004_5128_amd import workloads as W

@@ -155,20 +155,29 @@ void launch_adjoint_dots(const Problem &pb, const double *lam, const double *u, 
               k_lo, nk, grad);
 }
 
-// One workgroup: lane t sums entries t, t + 256, ... in order, then a fixed tree.
-__global__ __launch_bounds__(kAdjThreads) void adjoint_final_kernel(
-    const double *__restrict__ grad, int64_t n, double r, double alpha, double lndt, double dt,
-    double *__restrict__ dparams) {
-    __shared__ double red[3][kAdjThreads];
+// The per-step partial sums in two fixed-order stages: workgroup g of kAdjThreads sums the
+// entries [g len, (g + 1) len) (lane t: t, t + 256, ... of the range, in order, then the
+// tree), then one workgroup sums the kAdjThreads results of the first stage (one per lane,
+// then the tree) and forms the gradients.
+__global__ __launch_bounds__(kAdjThreads) void adjoint_final_partial_kernel(
+    const double *__restrict__ grad, int64_t n, int64_t len, double *__restrict__ part) {
+    const int64_t lo = (int64_t)blockIdx.x * len, hi = min(n, lo + len);
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += kAdjThreads) {
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kAdjThreads) {
         s0 += grad[i * 3 + 0];
         s1 += grad[i * 3 + 1];
         s2 += grad[i * 3 + 2];
     }
-    red[0][threadIdx.x] = s0;
-    red[1][threadIdx.x] = s1;
-    red[2][threadIdx.x] = s2;
+    adj_group_sums(s0, s1, s2, part + (int64_t)blockIdx.x * 3);
+}
+
+__global__ __launch_bounds__(kAdjThreads) void adjoint_final_kernel(
+    const double *__restrict__ part, double r, double alpha, double lndt, double dt,
+    double *__restrict__ dparams) {
+    __shared__ double red[3][kAdjThreads];
+    red[0][threadIdx.x] = part[threadIdx.x * 3 + 0];
+    red[1][threadIdx.x] = part[threadIdx.x * 3 + 1];
+    red[2][threadIdx.x] = part[threadIdx.x * 3 + 2];
     __syncthreads();
     for (int h = kAdjThreads / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
@@ -186,8 +195,12 @@ __global__ __launch_bounds__(kAdjThreads) void adjoint_final_kernel(
 }
 
 void launch_adjoint_final(const double *grad, int64_t n, double r, double alpha, double lndt,
-                          double dt, double *dparams, hipStream_t s) {
-    GL_LAUNCH(adjoint_final_kernel, dim3(1), dim3(kAdjThreads), 0, s, grad, n, r, alpha, lndt, dt,
+                          double dt, double *part, double *dparams, hipStream_t s) {
+    static_assert(kAdjFinalParts == kAdjThreads, "one first-stage sum per lane");
+    const int64_t len = (n + kAdjFinalParts - 1) / kAdjFinalParts;
+    GL_LAUNCH(adjoint_final_partial_kernel, dim3(kAdjFinalParts), dim3(kAdjThreads), 0, s, grad,
+              n, len, part);
+    GL_LAUNCH(adjoint_final_kernel, dim3(1), dim3(kAdjThreads), 0, s, part, r, alpha, lndt, dt,
               dparams);
 }
 

@@ -42,6 +42,7 @@ struct gl_ctx {
     double *adj_lam[2] = {nullptr, nullptr};  // plain path: lam[k + 1] and lam[k]
     double *adj_lamseg = nullptr;  // blocked path: lam[ks .. ke] of a segment, (C + 1) x max P
     double *adj_grad = nullptr;  // per step and workgroup partial dot products, 3 each
+    double *adj_fpart = nullptr; // the final reduction's first-stage sums, kAdjFinalParts x 3
     gl::Run *adj_runs = nullptr;  // adaptive memory: the transposed schedule's runs
     size_t adj_runs_cap = 0;
     // blocked adjoint (Toeplitz path): the sums over the mu rows before a block of reverse
@@ -749,7 +750,7 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
     const bool toep = ctx->opt.sum_path == GL_SUM_TOEPLITZ_BF16X3;
     size_t need = ((size_t)n * ctx->maxld) * sizeof(float) +
                   ((size_t)(3 * C + 1) * ctx->maxP + 2 * (size_t)ctx->maxP +
-                   (size_t)n * groups * 3) * sizeof(double);
+                   (size_t)n * groups * 3 + 3 * gl::kAdjFinalParts) * sizeof(double);
     if (toep) {
         need += (2 * (size_t)ctx->B + ctx->B2 + C + 1) * ctx->maxP * sizeof(double);
         for (const gl::Problem &pb : ctx->probs) need += 16 * (size_t)pb.tab_len * sizeof(uint16_t);
@@ -767,6 +768,7 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
     if ((st = dev_alloc(ctx, &ctx->adj_lam[0], ctx->maxP))) return st;
     if ((st = dev_alloc(ctx, &ctx->adj_lam[1], ctx->maxP))) return st;
     if ((st = dev_alloc(ctx, &ctx->adj_grad, (size_t)n * groups * 3))) return st;
+    if ((st = dev_alloc(ctx, &ctx->adj_fpart, (size_t)gl::kAdjFinalParts * 3))) return st;
     if (toep) {
         if ((st = dev_alloc(ctx, &ctx->adj_oldA, (size_t)ctx->B * ctx->maxP))) return st;
         if ((st = dev_alloc(ctx, &ctx->adj_oldG, (size_t)ctx->B * ctx->maxP))) return st;
@@ -929,7 +931,7 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
         HIP_TRY(ctx, hipMemcpyAsync(dL_du0 + pb.offset, toep ? lam_top : ctx->adj_lam[cur],
                                     P * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
         gl::launch_adjoint_final(ctx->adj_grad, n * groups, pb.r, pb.p.alpha, std::log(pb.p.dt),
-                                 pb.p.dt, dparams + 3 * ip, ctx->stream);
+                                 pb.p.dt, ctx->adj_fpart, dparams + 3 * ip, ctx->stream);
         HIP_TRY(ctx, hipGetLastError());
     }
     return GL_OK;

@@ -272,9 +272,11 @@ void launch_adjoint_dots(const Problem &pb, const double *lam, const double *u, 
 // Workgroups of one adjoint update launch for P points.
 int adjoint_groups(int64_t P);
 // dparams[0..2] = {dL/dalpha, dL/dgamma, dL/drate} from the per-step partial sums
-// grad[n * 3] (n entries in the fixed order they were written).
+// grad[n * 3] (n entries in the fixed order they were written), through part (the
+// kAdjFinalParts x 3 sums of a first stage over consecutive ranges).
+constexpr int kAdjFinalParts = 256;
 void launch_adjoint_final(const double *grad, int64_t n, double r, double alpha, double lndt,
-                          double dt, double *dparams, hipStream_t s);
+                          double dt, double *part, double *dparams, hipStream_t s);
 
 // *flag = 1 if any of x[0..n) is NaN or Inf (flag must start at 0).
 void launch_check_finite(const double *x, int64_t n, int *flag, hipStream_t s);
