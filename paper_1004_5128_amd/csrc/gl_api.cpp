@@ -51,6 +51,10 @@ struct gl_ctx {
     double *adj_oldA = nullptr, *adj_oldG = nullptr;  // B x max P each
     double *adj_oldA2 = nullptr;                       // B2 x max P (sub-block sums)
     int64_t adj_oldA_r0 = -1, adj_oldA2_r1 = -1;
+    // chain carries between the reverse in-block launches (as the forward's, own buffers)
+    double *adj_carry[2] = {nullptr, nullptr};         // kMaxFuse x max P each
+    int64_t adj_carry_rho = -1;                        // reverse step the carry starts at
+    int32_t adj_carry_n = 0, adj_carry_cur = 0;
     int64_t maxP = 0, maxld = 0;
     int B = 256;             // block length of the Toeplitz path
     int B2 = 0;              // sub-block length inside a block (0: one level)
@@ -752,7 +756,8 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
                   ((size_t)(3 * C + 1) * ctx->maxP + 2 * (size_t)ctx->maxP +
                    (size_t)n * groups * 3 + 3 * gl::kAdjFinalParts) * sizeof(double);
     if (toep) {
-        need += (2 * (size_t)ctx->B + ctx->B2 + C + 1) * ctx->maxP * sizeof(double);
+        need += (2 * (size_t)ctx->B + ctx->B2 + C + 1 + 2 * gl::kMaxFuse) * ctx->maxP *
+                sizeof(double);
         for (const gl::Problem &pb : ctx->probs) need += 16 * (size_t)pb.tab_len * sizeof(uint16_t);
     }
     size_t free_b = 0, total_b = 0;
@@ -775,6 +780,10 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
         if (ctx->B2 && (st = dev_alloc(ctx, &ctx->adj_oldA2, (size_t)ctx->B2 * ctx->maxP)))
             return st;
         if ((st = dev_alloc(ctx, &ctx->adj_lamseg, (size_t)(C + 1) * ctx->maxP))) return st;
+        if (carry_ok(ctx))
+            for (int c = 0; c < 2; ++c)
+                if ((st = dev_alloc(ctx, &ctx->adj_carry[c], (size_t)gl::kMaxFuse * ctx->maxP)))
+                    return st;
         // d psi / d gamma tables (zero past a short-memory window, as the psi tables)
         const int64_t npsi = ctx->opt.max_steps + gl::kMaxBlock + 1;
         const int64_t nkeep = ctx->opt.mem_mode == GL_MEM_SHORT
@@ -850,9 +859,9 @@ gl_status adjoint_segment_blocked(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int6
             ctx->adj_oldA2_r1 = r1;
         }
         const int64_t s = std::max<int64_t>(1, std::min({max_s, sub_len - c, k - ks + 1}));
-        gl::AdjStepArgs args{};
+        gl::BlockStepArgs args{};
         args.psi = pb.psi_blk;
-        args.M = ctx->adj_M;
+        args.H = ctx->adj_M;
         args.ld = pb.ld;
         args.P = P;
         args.ndim = pb.p.ndim;
@@ -863,14 +872,41 @@ gl_status adjoint_segment_blocked(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int6
         args.r = pb.r;
         args.dt = pb.p.dt;
         args.rate = pb.p.rxn_rate;
-        args.base = (r1 > r0 ? ctx->adj_oldA2 : ctx->adj_oldA) + c * P;
-        args.lam_in = ctx->adj_lamseg + (k + 1 - ks) * P;
-        args.lam_out = ctx->adj_lamseg + (k - ks) * P;
-        args.u = ctx->adj_u + (k - ks) * P;
-        args.rho = rho;
-        args.c = (int32_t)c;
+        args.pre = (r1 > r0 ? ctx->adj_oldA2 : ctx->adj_oldA) + c * P;
+        args.pre_row = 0;
+        args.has_pre = 1;  // zero sums before the first block
+        args.u_cur = ctx->adj_lamseg + (k + 1 - ks) * P;
+        args.lam_rows = ctx->adj_lamseg + (k - ks) * P;
+        args.u_rev = ctx->adj_u + (k - ks) * P;
+        args.k = rho;
+        args.b = (int32_t)(rho - r0);
+        args.b2 = (int32_t)c;
         args.s = (int32_t)s;
+        args.write_history = 1;
+        // chain carries between consecutive launches of a sub-block, as on the forward (the
+        // sweep runs the sub-block's launches in order, across segment boundaries too: the
+        // recomputation in between uses the forward's own carry buffers)
+        int out_buf = 0;
+        if (carry_ok(ctx)) {
+            if (ctx->adj_carry_rho == rho && s <= ctx->adj_carry_n) {
+                args.carry_in = ctx->adj_carry[ctx->adj_carry_cur];
+                out_buf = ctx->adj_carry_cur ^ 1;
+            } else if (c == 0) {
+                args.carry_in = args.pre;  // a sub-block's chains start at the sums before it
+            }
+            if (c + s < sub_len) {
+                args.carry_out = ctx->adj_carry[out_buf];
+                args.n_next = (int32_t)std::min<int64_t>(max_s, sub_len - (c + s));
+            }
+        }
         gl::launch_adjoint_steps(args, ctx->stream);
+        if (args.carry_out) {
+            ctx->adj_carry_rho = rho + s;
+            ctx->adj_carry_n = args.n_next;
+            ctx->adj_carry_cur = out_buf;
+        } else {
+            ctx->adj_carry_rho = -1;
+        }
         k -= s;
     }
     gl::launch_adjoint_dots(pb, ctx->adj_lamseg, ctx->adj_u, ctx->adj_S, ctx->adj_G, ks, ke - ks,
@@ -896,6 +932,7 @@ gl_status adjoint_impl(gl_ctx *ctx, const double *dL_duT, double *dL_du0, double
         const double *lam_top = dL_duT + pb.offset;  // lam at the top of the next segment
         int cur = 0;
         ctx->adj_oldA_r0 = ctx->adj_oldA2_r1 = -1;  // block sums of this problem's mu history
+        ctx->adj_carry_rho = -1;
         if (!toep)
             HIP_TRY(ctx, hipMemcpyAsync(ctx->adj_lam[0], lam_top, P * sizeof(double),
                                         hipMemcpyDeviceToDevice, ctx->stream));

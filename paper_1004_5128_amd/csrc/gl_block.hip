@@ -76,7 +76,14 @@ __device__ __forceinline__ double step_reaction(int rxn, double rate, double u) 
     return 0.0;
 }
 
-template <int S, bool D3, bool kFromCarry>
+// f'(u), for the reverse steps
+__device__ __forceinline__ double step_reaction_slope(int rxn, double rate, double u) {
+    if (rxn == GL_RXN_LINEAR) return -rate;
+    if (rxn == GL_RXN_FISHER) return rate * (1.0 - 2.0 * u);
+    return 0.0;
+}
+
+template <int S, bool D3, bool kFromCarry, bool kRev>
 __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
     using G = StepGeom<S, D3>;
     __shared__ double lu[2][G::kULen];
@@ -172,6 +179,16 @@ __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
         const char *o = reinterpret_cast<const char *>(cstart + (int64_t)(crow + min(i, s - 1)) * P);
 #pragma unroll
         for (int n = 0; n < G::kPts; ++n) pv[n][i] = *reinterpret_cast<const double *>(o + qb8[n]);
+    }
+    // reverse steps: u of forward step kf - i, for f' (issued with the other loads)
+    double urv[G::kPts][kRev ? S : 1];
+    if constexpr (kRev) {
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+#pragma unroll
+            for (int n = 0; n < G::kPts; ++n)
+                urv[n][i] = *reinterpret_cast<const double *>(
+                    reinterpret_cast<const char *>(a.u_rev - (int64_t)min(i, s - 1) * P) + qb8[n]);
     }
     const int nr = a.b2;  // rows k - nr .. k - 1
     const float *rows = a.H + (k - nr) * a.ld;
@@ -294,31 +311,46 @@ __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
         const int64_t kk = k + i;
 #pragma unroll
         for (int n = 0; n < G::kPts; ++n) {
+            // no contraction of the step's products into sums: every instantiation (S, carry,
+            // forward or reverse) then rounds the same operations in the written order, which
+            // the bitwise grouping guarantee needs (the chains use explicit fma)
+#pragma clang fp contract(off)
             if (lvl[n] < i) continue;
             const int x = ux[n];
-            const double u = uc[x];
-            const double d =
+            const double u = uc[x];  // lam[kf - i + 1] for reverse steps
+            const double lap =
                 D3    ? uc[x + 1] + uc[x - 1] + uc[x + uw] + uc[x - uw] + uc[x + uwh] +
                             uc[x - uwh] - 6.0 * u
                 : two ? uc[x + 1] + uc[x - 1] - 4.0 * u + uc[x + uw] + uc[x - uw]
                       : uc[x + 1] - 2.0 * u + uc[x - 1];
+            // the history row: delta = Lap u, or for reverse steps mu = r Lap lam
+            const double d = kRev ? a.r * lap : lap;
             double c = acc[n][i];
 #pragma unroll
             for (int i2 = 0; i2 < i; ++i2) c = fma(wl[i - i2], (double)dl[n][i2], c);
             const float df = (float)d;
             dl[n][i] = df;
             const double Sv = c + d;
-            const double unew = u + a.dt * step_reaction(a.rxn, a.rate, u) + a.r * Sv;
+            double unew;
+            if constexpr (kRev)  // lam[kf - i] = lam + dt f'(u[kf - i]) lam + sum psi(m) mu
+                unew = u + a.dt * step_reaction_slope(a.rxn, a.rate, urv[n][i]) * u + Sv;
+            else
+                unew = u + a.dt * step_reaction(a.rxn, a.rate, u) + a.r * Sv;
             un[x] = unew;
             if (lvl[n] >= S - 1) {  // a point of the tile: results go out
                 if (to_carry) lrows[nr + i][tl[n]] = df;  // nr + i < nr + s <= kRowBatch
                 if (a.write_history) a.H[kk * a.ld + q[n]] = df;
-                if (a.S_out) a.S_out[(int64_t)i * P + q[n]] = Sv;
-                if (i == s - 1) a.u_next[q[n]] = unew;
-                else if (a.u_rows) a.u_rows[(int64_t)i * a.u_stride + q[n]] = unew;
-                if ((a.snap_mask >> i) & 1u)
-                    a.snap[(a.snap_row0 + __builtin_popcount(a.snap_mask & ((1u << i) - 1u))) * P +
-                           q[n]] = unew;
+                if constexpr (kRev) {
+                    a.lam_rows[q[n] - (int64_t)i * P] = unew;
+                } else {
+                    if (a.S_out) a.S_out[(int64_t)i * P + q[n]] = Sv;
+                    if (i == s - 1) a.u_next[q[n]] = unew;
+                    else if (a.u_rows) a.u_rows[(int64_t)i * a.u_stride + q[n]] = unew;
+                    if ((a.snap_mask >> i) & 1u)
+                        a.snap[(a.snap_row0 +
+                                __builtin_popcount(a.snap_mask & ((1u << i) - 1u))) * P +
+                               q[n]] = unew;
+                }
             }
         }
     }
@@ -355,7 +387,12 @@ __device__ __forceinline__ void block_steps_body(const BlockStepArgs &a) {
 
 template <int S, bool C>
 __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs a) {
-    block_steps_body<S, false, C>(a);
+    block_steps_body<S, false, C, false>(a);
+}
+
+template <int S, bool C>
+__global__ __launch_bounds__(kStepThreads) void adjoint_steps_kernel(BlockStepArgs a) {
+    block_steps_body<S, false, C, true>(a);
 }
 
 // A 3D grid has four times the tiles of a 2D grid of the same size: at most 64 VGPRs
@@ -363,182 +400,14 @@ __global__ __launch_bounds__(kStepThreads) void block_steps_kernel(BlockStepArgs
 template <int S, bool C>
 __global__ __launch_bounds__(kStepThreads) __attribute__((amdgpu_waves_per_eu(8)))
 void block_steps_kernel_3d(BlockStepArgs a) {
-    block_steps_body<S, true, C>(a);
+    block_steps_body<S, true, C, false>(a);
 }
 
-// ---- reverse steps (adjoint) on the same tiles
-//
-// lam[k] = lam[k+1] + dt f'(u[k]) lam[k+1] + sum_{m >= 0} psi(m) mu[k+m], mu[k] = r Lap lam[k+1]:
-// in reverse time rho = n - 1 - k the mu rows are a history like the forward's delta rows, so
-// reverse step rho + i of a launch takes the forward's in-block chain (the base row, then the
-// sub-block's mu rows in ascending order, the launch's own rows from registers, mu itself
-// last) and the halo scheme above, with lam in place of u.  u[k - i] enters through f'
-// only, read at each point from the segment's recomputed states.
-__device__ __forceinline__ double adj_reaction_slope(int rxn, double rate, double u) {
-    if (rxn == GL_RXN_LINEAR) return -rate;
-    if (rxn == GL_RXN_FISHER) return rate * (1.0 - 2.0 * u);
-    return 0.0;
-}
-
-template <int S, bool D3>
-__device__ __forceinline__ void adjoint_steps_body(const AdjStepArgs &a) {
-    using G = StepGeom<S, D3>;
-    __shared__ double ll[2][G::kULen];
-    const int tid = threadIdx.x;
-    const bool two = !D3 && a.ndim == 2;
-    const int tx = D3 ? kTile3x : two ? kTile2 : kTile1;
-    const int ty = D3 ? kTile3y : two ? kTile2 : 1, tz = D3 ? kTile3z : 1;
-    const int hy = D3 || two ? 1 : 0;
-    constexpr int hz = D3 ? 1 : 0;
-    const int uw = tx + 2 * S, uh = ty + 2 * S * hy, ud = tz + 2 * S * hz;
-    const int w0 = tx + 2 * (S - 1), h0 = ty + 2 * (S - 1) * hy;
-    const int d0 = tz + 2 * (S - 1) * hz;
-    const int uwh = uw * uh, w0h0 = w0 * h0;
-    const int64_t nx = a.nx, ny = hy ? a.ny : 1, nz = D3 ? a.nz : 1, P = a.P;
-    const int ntx = (int)((nx + tx - 1) / tx), nty = (int)((ny + ty - 1) / ty);
-    const int tile = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    const int tix = tile % ntx, trest = tile / ntx;
-    const int tiy = D3 ? trest % nty : trest, tiz = D3 ? trest / nty : 0;
-    const int64_t gx0 = (int64_t)tix * tx - S;
-    const int64_t gy0 = (int64_t)tiy * ty - S * hy;
-    const int64_t gz0 = (int64_t)tiz * tz - S * hz;
-    const int s = a.s;
-
-    // lam[k + 1] on the region widened by S (zero outside the grid)
-    constexpr int kULoads = (G::kULen + kStepThreads - 1) / kStepThreads;
-    double lv[kULoads];
-    bool lin[kULoads];
-#pragma unroll
-    for (int c = 0; c < kULoads; ++c) {
-        const int idx = tid + c * kStepThreads;
-        const int iz = D3 ? idx / uwh : 0, ixy = idx - iz * uwh;
-        const int64_t gx = gx0 + ixy % uw, gy = gy0 + ixy / uw, gz = gz0 + iz;
-        lin[c] = idx < uwh * ud && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 &&
-                 gz < nz;
-        lv[c] = a.lam_in[lin[c] ? (gz * ny + gy) * nx + gx : 0];
-    }
-
-    int ux[G::kPts], lvl[G::kPts];
-    int64_t q[G::kPts];
-#pragma unroll
-    for (int n = 0; n < G::kPts; ++n) {
-        const int r = tid + n * kStepThreads;
-        const int rz = D3 ? r / w0h0 : 0, rxy = r - rz * w0h0;
-        const int rx = rxy % w0, ry = rxy / w0;
-        const int64_t gx = gx0 + rx + 1, gy = gy0 + ry + hy, gz = gz0 + rz + hz;
-        const bool ok = r < w0h0 * d0 && gx >= 0 && gx < nx && gy >= 0 && gy < ny && gz >= 0 &&
-                        gz < nz;
-        int l = min(rx, w0 - 1 - rx);
-        if (hy) l = min(l, min(ry, h0 - 1 - ry));
-        if (D3) l = min(l, min(rz, d0 - 1 - rz));
-        lvl[n] = ok ? l : -1;
-        ux[n] = ((rz + hz) * uh + ry + hy) * uw + rx + 1;
-        q[n] = ok ? (gz * ny + gy) * nx + gx : 0;
-    }
-
-    // chain starts (base rows), the states u[k - i] and the sub-block's mu rows, all issued
-    // before use; slots without a grid point read point 0, steps past s re-read step s - 1's
-    // rows, rows past the last re-read it (all unused)
-    double acc[G::kPts][S], uk[G::kPts][S];
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-        const int ic = min(i, s - 1);
-#pragma unroll
-        for (int n = 0; n < G::kPts; ++n) {
-            acc[n][i] = a.base[(int64_t)ic * P + q[n]];
-            uk[n][i] = a.u[q[n] - (int64_t)ic * P];
-        }
-    }
-    const int nr = a.c;  // rows rho - nr .. rho - 1
-    const float *rows = a.M + (a.rho - nr) * a.ld;
-    for (int j = 0; j < nr; j += kRowBatch) {
-        float v[G::kPts][kRowBatch];
-#pragma unroll
-        for (int t = 0; t < kRowBatch; ++t) {
-            const float *row = rows + (int64_t)min(j + t, nr - 1) * a.ld;
-#pragma unroll
-            for (int n = 0; n < G::kPts; ++n) v[n][t] = row[q[n]];
-        }
-#pragma unroll
-        for (int h = 0; h < kRowBatch / kWin; ++h) {
-            const int j0 = j + h * kWin;
-            if (j0 >= nr) continue;
-            // row j0 + t is m = nr - j0 - t + i steps back from reverse step rho + i
-            double w[kWin + S - 1];
-#pragma unroll
-            for (int x = 0; x < kWin + S - 1; ++x) w[x] = a.psi[max(nr - j0 - (kWin - 1) + x, 0)];
-#pragma unroll
-            for (int t = 0; t < kWin; ++t) {
-                if (j0 + t < nr) {
-#pragma unroll
-                    for (int i = 0; i < S; ++i) {
-                        if (i < s) {
-#pragma unroll
-                            for (int n = 0; n < G::kPts; ++n)
-                                acc[n][i] = fma(w[kWin - 1 - t + i], (double)v[n][h * kWin + t],
-                                                acc[n][i]);
-                        }
-                    }
-                }
-            }
-        }
-    }
-    double wl[S];  // psi(1 .. S-1) for the launch's own rows
-#pragma unroll
-    for (int m = 1; m < S; ++m) wl[m] = m < s ? a.psi[m] : 0.0;
-    wl[0] = 0.0;
-
-#pragma unroll
-    for (int c = 0; c < kULoads; ++c) {
-        const int idx = tid + c * kStepThreads;
-        if (idx < uwh * ud) {
-            ll[0][idx] = lin[c] ? lv[c] : 0.0;
-            ll[1][idx] = 0.0;
-        }
-    }
-
-    float ml[G::kPts][S];  // the lane's mu rows rho .. rho + i - 1, FP32 as stored
-#pragma unroll
-    for (int i = 0; i < S; ++i) {
-        if (i >= s) break;
-        __syncthreads();  // lam[k - i + 1] complete in ll[i & 1]; its readers of step i - 1 done
-        const double *lc = ll[i & 1];
-        double *ln = ll[(i & 1) ^ 1];
-#pragma unroll
-        for (int n = 0; n < G::kPts; ++n) {
-            if (lvl[n] < i) continue;
-            const int x = ux[n];
-            const double l1 = lc[x];
-            const double lap =
-                D3    ? lc[x + 1] + lc[x - 1] + lc[x + uw] + lc[x - uw] + lc[x + uwh] +
-                            lc[x - uwh] - 6.0 * l1
-                : two ? lc[x + 1] + lc[x - 1] - 4.0 * l1 + lc[x + uw] + lc[x - uw]
-                      : lc[x + 1] - 2.0 * l1 + lc[x - 1];
-            const double mu = a.r * lap;
-            double c = acc[n][i];
-#pragma unroll
-            for (int i2 = 0; i2 < i; ++i2) c = fma(wl[i - i2], (double)ml[n][i2], c);
-            const float mf = (float)mu;
-            ml[n][i] = mf;
-            const double lnew = l1 + a.dt * adj_reaction_slope(a.rxn, a.rate, uk[n][i]) * l1 +
-                                (c + mu);
-            ln[x] = lnew;
-            if (lvl[n] >= S - 1) {  // a point of the tile: results go out
-                a.M[(a.rho + i) * a.ld + q[n]] = mf;
-                a.lam_out[q[n] - (int64_t)i * P] = lnew;
-            }
-        }
-    }
-}
-
-template <int S>
-__global__ __launch_bounds__(kStepThreads) void adjoint_steps_kernel(AdjStepArgs a) {
-    adjoint_steps_body<S, false>(a);
-}
-
-template <int S>
-__global__ __launch_bounds__(kStepThreads) void adjoint_steps_kernel_3d(AdjStepArgs a) {
-    adjoint_steps_body<S, true>(a);
+// the reverse steps hold u[kf - i] as well: without the eight-wave bound (one workgroup per
+// CU), so that they do not spill
+template <int S, bool C>
+__global__ __launch_bounds__(kStepThreads) void adjoint_steps_kernel_3d(BlockStepArgs a) {
+    block_steps_body<S, true, C, true>(a);
 }
 
 int64_t step_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz) {
@@ -548,26 +417,10 @@ int64_t step_tiles(int ndim, int64_t nx, int64_t ny, int64_t nz) {
                        : (nx + kTile1 - 1) / kTile1;
 }
 
-void launch_adjoint_steps(const AdjStepArgs &args, hipStream_t s) {
-    const dim3 grid((unsigned)step_tiles(args.ndim, args.nx, args.ny, args.nz)),
-        block(kStepThreads);
-    if (args.ndim == 3) {  // s <= kMaxFuse3, checked by the caller
-        if (args.s <= 1)
-            GL_LAUNCH((adjoint_steps_kernel_3d<1>), grid, block, 0, s, args);
-        else
-            GL_LAUNCH((adjoint_steps_kernel_3d<2>), grid, block, 0, s, args);
-    } else if (args.s <= 1) {
-        GL_LAUNCH((adjoint_steps_kernel<1>), grid, block, 0, s, args);
-    } else if (args.s <= 2) {
-        GL_LAUNCH((adjoint_steps_kernel<2>), grid, block, 0, s, args);
-    } else if (args.s <= 4) {
-        GL_LAUNCH((adjoint_steps_kernel<4>), grid, block, 0, s, args);
-    } else {
-        GL_LAUNCH((adjoint_steps_kernel<8>), grid, block, 0, s, args);
-    }
-}
-
-void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
+// The in-block kernels for s steps (at most kMaxFuse3 in 3D, checked by the caller), in the
+// variant that starts from a carry when the arguments hold one.
+template <template <int, bool> class K2, template <int, bool> class K3>
+void dispatch_steps(const BlockStepArgs &args, hipStream_t s) {
     const dim3 grid((unsigned)step_tiles(args.ndim, args.nx, args.ny, args.nz)),
         block(kStepThreads);
     static_assert(kMaxFuse3 == 2, "3D instantiations");
@@ -575,25 +428,38 @@ void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
 #define GL_STEP_CASE(kern, S)                                                                  \
     do {                                                                                       \
         if (c)                                                                                 \
-            GL_LAUNCH((kern<S, true>), grid, block, 0, s, args);                               \
+            GL_LAUNCH((kern<S, true>::fn), grid, block, 0, s, args);                           \
         else                                                                                   \
-            GL_LAUNCH((kern<S, false>), grid, block, 0, s, args);                              \
+            GL_LAUNCH((kern<S, false>::fn), grid, block, 0, s, args);                          \
     } while (0)
-    if (args.ndim == 3) {  // s <= kMaxFuse3, checked by the caller
+    if (args.ndim == 3) {
         if (args.s <= 1)
-            GL_STEP_CASE(block_steps_kernel_3d, 1);
+            GL_STEP_CASE(K3, 1);
         else
-            GL_STEP_CASE(block_steps_kernel_3d, 2);
+            GL_STEP_CASE(K3, 2);
     } else if (args.s <= 1) {
-        GL_STEP_CASE(block_steps_kernel, 1);
+        GL_STEP_CASE(K2, 1);
     } else if (args.s <= 2) {
-        GL_STEP_CASE(block_steps_kernel, 2);
+        GL_STEP_CASE(K2, 2);
     } else if (args.s <= 4) {
-        GL_STEP_CASE(block_steps_kernel, 4);
+        GL_STEP_CASE(K2, 4);
     } else {
-        GL_STEP_CASE(block_steps_kernel, 8);
+        GL_STEP_CASE(K2, 8);
     }
 #undef GL_STEP_CASE
+}
+
+template <int S, bool C> struct Fwd2 { static constexpr auto fn = block_steps_kernel<S, C>; };
+template <int S, bool C> struct Fwd3 { static constexpr auto fn = block_steps_kernel_3d<S, C>; };
+template <int S, bool C> struct Rev2 { static constexpr auto fn = adjoint_steps_kernel<S, C>; };
+template <int S, bool C> struct Rev3 { static constexpr auto fn = adjoint_steps_kernel_3d<S, C>; };
+
+void launch_block_step(const BlockStepArgs &args, hipStream_t s) {
+    dispatch_steps<Fwd2, Fwd3>(args, s);
+}
+
+void launch_adjoint_steps(const BlockStepArgs &args, hipStream_t s) {
+    dispatch_steps<Rev2, Rev3>(args, s);
 }
 
 }  // namespace gl

@@ -215,6 +215,14 @@ struct BlockStepArgs {
     const double *carry_in;
     double *carry_out;
     int32_t n_next;
+    // Reverse steps (the adjoint, through launch_adjoint_steps): k is the first reverse step
+    // rho and the s steps are those of forward steps kf = n - 1 - rho down to kf - s + 1.
+    // u_cur is lam[kf + 1], H the mu history (row rho + i written by reverse step rho + i),
+    // pre the sums over the mu rows before the sub-block (pre_row 0, has_pre 1); u_rev holds
+    // u[kf - i] at u_rev - i P and lam_rows receives lam[kf - i] at lam_rows - i P (the rows
+    // descend in memory).  The forward-only outputs (u_next, u_rows, S_out, snap) are unused.
+    const double *u_rev;
+    double *lam_rows;
 };
 
 constexpr int kMaxFuse = 8;
@@ -243,26 +251,13 @@ void launch_adjoint_update(const Problem &pb, const double *lam1, double *lam0, 
                            const double *Gk, double *grad, hipStream_t s);
 
 // Reverse steps rho .. rho + s - 1 of one sub-block on the blocked path (forward steps
-// k, k - 1, .. k - s + 1, k = n - 1 - rho), in one launch with the in-block kernel's tiles and
-// halos.  The sum of reverse step rho + i over the mu history runs as the forward's in-block
-// chain: base row i, then psi(m) times the mu rows rho - c .. rho + i - 1 in ascending order,
-// then mu[k - i] itself (psi(0) = 1); the result does not depend on how the steps are grouped.
-struct AdjStepArgs {
-    const double *psi;    // psi, zero past a short-memory window
-    float *M;             // mu history in reverse time (stride ld): reads rows rho - c ..
-                          // rho - 1, writes rows rho .. rho + s - 1
-    int64_t ld, P;
-    int32_t ndim, nx, ny, nz, rxn;
-    double r, dt, rate;
-    const double *base;   // row i (stride P): the sums over the mu rows before rho - c
-    const double *lam_in; // lam[k + 1]
-    double *lam_out;      // lam[k - i] goes to lam_out - i P (the rows descend in memory)
-    const double *u;      // u[k - i] at u - i P
-    int64_t rho;
-    int32_t c;            // mu rows summed from the history (rho - c .. rho - 1)
-    int32_t s;            // 1 .. kMaxFuse (kMaxFuse3 in 3D)
-};
-void launch_adjoint_steps(const AdjStepArgs &args, hipStream_t s);
+// kf, kf - 1, .. kf - s + 1, kf = n - 1 - rho), in one launch of the in-block kernel with
+// lam in place of u and mu = r Lap lam in place of delta: the sum of reverse step rho + i
+// over the mu history runs as the forward's chain (the sums before the sub-block, then
+// psi(m) times the mu rows rho - b2 .. rho + i - 1 in ascending order, then mu itself,
+// psi(0) = 1), chain carries between launches included, so the result does not depend on
+// how the steps are grouped.  Arguments as BlockStepArgs describes for reverse steps.
+void launch_adjoint_steps(const BlockStepArgs &args, hipStream_t s);
 
 // Per-workgroup partial sums for the steps k = k_lo .. k_lo + nk - 1 of a segment, as the
 // plain path's update forms them: lam1 * S, lam1 * G, lam1 * df/drate(u) with lam1 row
