@@ -125,7 +125,8 @@ def test_blocked_adjoint_does_not_depend_on_grouping(ndim):
     target = np.zeros_like(u0)
     print_case("blocked adjoint grouping", ndim)
     outs = []
-    for C, fuse in [(n, 8), (10, 8), (7, 3), (33, 1), (64, 5), (1, 2)]:
+    # (n, 2): every launch takes two steps, the instantiation that once rounded differently
+    for C, fuse in [(n, 8), (10, 8), (7, 3), (33, 1), (64, 5), (1, 2), (n, 2)]:
         with env("GL_FUSE", fuse):
             outs.append(blocked_adjoint(p, mem, u0, n, target, C, 64))
     for o in outs[1:]:

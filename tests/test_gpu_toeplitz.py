@@ -135,7 +135,7 @@ def test_split_calls_equal_one_call():
                                          ((1, 600, 1), 32, 32), ((2, 20, 17), 128, 0),
                                          ((1, 300, 1), 256, 64), ((2, 24, 24), 512, 32)])
 def test_fused_steps_do_not_depend_on_grouping(dims, B, sub):
-    # the in-block steps taken 1, 3 or 8 per launch, and the run cut into calls of odd
+    # the in-block steps taken 1, 2, 3 or 8 per launch, and the run cut into calls of odd
     # lengths, give the same bits: each step's sum is one chain that does not depend on
     # where a launch starts (sub = 0: one level, rows up to B - 1 summed in the step kernel)
     ndim, nx, ny = dims
@@ -146,7 +146,7 @@ def test_fused_steps_do_not_depend_on_grouping(dims, B, sub):
     print_case("fused grouping", dims, B, sub)
     outs = []
     with env("GL_SUBBLOCK", sub):
-        for fuse in (1, 3, 8):
+        for fuse in (1, 2, 3, 8):
             with env("GL_FUSE", fuse):
                 outs.append(gpu_run(p, W.memory("full"), u0, n, sum_path="toeplitz", block_B=B))
         with env("GL_FUSE", 8), gl().Solver(p, W.memory("full"), torch.as_tensor(u0),
