@@ -5,7 +5,8 @@ gl_adjoint (the reverse-time sweep with transposed GL weights and d psi / d gamm
 
 u0 is a CUDA float64 tensor; alpha, gamma and rate are 0-dim tensors (any device); the
 problem dict supplies the grid, dt, dx and reaction kind (its own alpha, gamma and rate
-are replaced by the tensor values).  dt and dx are held fixed.  Full and short memory.
+are replaced by the tensor values).  dt and dx are held fixed.  Every memory mode (adaptive
+memory through the transposed schedule) and both history-sum paths.
 """
 import torch
 
