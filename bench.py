@@ -49,12 +49,14 @@ def prefix_steps(P):
     return max(100, int(round(np.sqrt(2 * PREFIX_MACS / P) / 100)) * 100)
 
 
-WORKLOADS = ("2d_256", "superdiffusion_2d", "diffusion_3d", "fisher_512")
+WORKLOADS = ("2d_256", "superdiffusion_2d", "diffusion_3d", "fisher_512", "ensemble64")
 WORKLOAD_NAMES = {
     "2d_256": "2d_256x256_gamma0.8_alpha1_linear0.1_gaussian_r0.1_20000steps_full",
     "superdiffusion_2d": "2d_256x256_gamma1.5_alpha1_none_gaussian_r0.1_20000steps_full",
     "diffusion_3d": "3d_64x64x64_gamma0.8_alpha1_linear0.1_gaussian_r0.05_20000steps_full",
-    "fisher_512": "2d_512x512_gamma0.6_alpha0.5_fisher1_uniform0.1_r0.1_50000steps_full"}
+    "fisher_512": "2d_512x512_gamma0.6_alpha0.5_fisher1_uniform0.1_r0.1_50000steps_full",
+    "ensemble64": "ensemble_64x2d_sides64-384_gamma0.3-0.95_linear_sine_r0.1_10000steps_adaptive_a4"}
+ENSEMBLE_CPU_STEPS = 320   # oracle sample: every member's first 320 steps (about 4e10 MACs)
 MODES = [(1, 1), (1, 3), (3, 1), (3, 3), (1, 5), (5, 5)]
 
 
@@ -544,6 +546,100 @@ def run_extra_workloads(block_B, with_oracle):
     return out
 
 
+def run_ensemble(args):
+    """The batched ensemble: 64 2D problems (sides 64 .. 384, 3 489 792 points), gamma, alpha
+    and reaction rate drawn per member, sine-mode initial states, adaptive memory (a = 4),
+    10 000 steps on the plain path, where each step is one batched GEMV and one batched update
+    launch over all members.  Prints the contract's line: history MACs/s of the timed solves,
+    the GEMV's roofline from a profiled solve, each member against the oracle's sine-mode
+    recursion over the full length and against the oracle's run over a prefix, and the
+    oracle's own rate on that prefix (every member, ENSEMBLE_CPU_STEPS steps)."""
+    import torch
+    from paper_1004_5128_amd import gl, workloads as W
+    w = W.cfg5()
+    probs, mem, n = w["problems"], w["memory"], w["nsteps"]
+    sizes = [W.npoints(p) for p in probs]
+    P = sum(sizes)
+    u0 = torch.as_tensor(np.concatenate(w["u0s"]), dtype=torch.float64).cuda()
+    s = gl.Solver(probs, mem, u0, max_steps=n)
+    terms = [s.schedule_terms(k) for k in range(n)]   # the schedule depends on k only
+    macs = P * sum(terms)
+    work = {"hist_gemv": ("hbm", 4 * P * sum(t - 1 for t in terms)),
+            "update": ("hbm", 20 * P * n)}
+    for i in range(args.warmup):
+        log("ensemble warmup", i)
+        s.reset(u0)
+        s.advance(n)
+    torch.cuda.synchronize()
+    log("ensemble timed", args.steps)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.reset(u0)
+        s.advance(n)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    uT = s.state().cpu().numpy()
+    log("ensemble profiled solve")
+    s.set_profiling(True)
+    s.reset(u0)
+    s.advance(n)
+    torch.cuda.synchronize()
+    prof = s.profile()
+    s.set_profiling(False)
+    n_cpu = min(ENSEMBLE_CPU_STEPS, n)
+    s.reset(u0)
+    s.advance(n_cpu)
+    u_pre = s.state().cpu().numpy()
+    s.close()
+    kernels = {}
+    for name, (cnt, kms) in prof.items():
+        if cnt:
+            kd = {"launches": cnt, "ms_per_solve": kms, "avg_us": kms * 1e3 / cnt}
+            if name in work:
+                kd["roofline"] = roofline_of(work[name][0], work[name][1], cnt, kms)
+            kernels[name] = kd
+    roofline = dict(kernels["hist_gemv"]["roofline"], kernel="hist_gemv")
+    d = {"ms_per_step": ms, "value": macs / (ms / 1e3), "kernels": kernels,
+         "traffic_note": "no counter run on this workload: traffic is null"}
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("oracle: every member,", n_cpu, "steps, and the sine-mode recursions")
+        worst_pre = worst_mode = 0.0
+        t_cpu = 0.0
+        off = 0
+        for i, (p, (a, b)) in enumerate(zip(probs, w["modes"])):
+            t1 = time.perf_counter()
+            ref = oracle.run(p, mem, w["u0s"][i], n_cpu)
+            t_cpu += time.perf_counter() - t1
+            got = u_pre[off:off + sizes[i]]
+            worst_pre = max(worst_pre, float(np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+            v = oracle.mode_run(p, mem, a, b, 1.0, n)[-1] * w["u0s"][i]
+            got = uT[off:off + sizes[i]]
+            worst_mode = max(worst_mode, float(np.linalg.norm(got - v) / np.linalg.norm(v)))
+            off += sizes[i]
+        d["worst_member_rel_l2_vs_oracle_prefix"] = worst_pre
+        d["worst_member_rel_l2_vs_oracle_mode_full_length"] = worst_mode
+        macs_cpu = P * sum(terms[:n_cpu])
+        cpu = {"value": macs_cpu / t_cpu, "unit": "history MACs/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "first %d of the %d steps of every member of the same ensemble (%.3g "
+                         "MACs, %.1f s)" % (n_cpu, n, macs_cpu, t_cpu)}
+    line = {
+        "metric": "history MACs/s + rel-L2 vs FP64 oracle; plain FP32 sum vs blocked MFMA sum",
+        "value": macs / (ms / 1e3), "unit": "history MACs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 history, f64 accumulate", "data": "synthetic",
+        "config": {"workload": WORKLOAD_NAMES["ensemble64"], "problems": len(probs),
+                   "points": P, "time_steps": n, "memory": "adaptive a=4",
+                   "history_macs_per_solve": macs, "path": "gemv"},
+        "paths": {"gemv": d},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def probe_hipblaslt(reps=10):
     """Vendor BF16 GEMMs (torch.matmul -> hipBLASLt) on the same GPU for comparison: square
     4096..16384 and the block product's shape (256 x 19968) x (19968 x 65536)."""
@@ -630,6 +726,9 @@ def main():
         sys.exit(2)
     if args.adjoint_only:
         print(json.dumps({"adjoint_128x128_5000steps": run_adjoint_leg()}), flush=True)
+        return
+    if args.workload == "ensemble64":
+        run_ensemble(args)
         return
 
     import torch
