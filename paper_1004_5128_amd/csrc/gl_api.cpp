@@ -240,6 +240,7 @@ gl_status apply_gemv_target(gl_ctx *ctx, int64_t groups) {
     const int32_t nprob = (int32_t)ctx->probs.size();
     std::vector<gl::BatchEntry> tab(nprob);
     size_t off = 0;
+    int64_t upd_begin = 0;
     for (int32_t i = 0; i < nprob; ++i) {
         gl::Problem &pb = ctx->probs[i];
         pb.gemv_groups = std::max<int64_t>(
@@ -255,6 +256,8 @@ gl_status apply_gemv_target(gl_ctx *ctx, int64_t groups) {
         e.partial = ctx->bpartial + off;
         e.snap = pb.snap;
         e.groups = pb.gemv_groups;
+        e.upd_begin = upd_begin;
+        upd_begin += (pb.P + 255) / 256;
         off += (size_t)splits * pb.P;
         e.ndim = pb.p.ndim;
         e.nx = pb.p.nx;
@@ -267,6 +270,9 @@ gl_status apply_gemv_target(gl_ctx *ctx, int64_t groups) {
     }
     if (off > ctx->bpart_cap)
         return fail(ctx, GL_EINVAL, "internal: batched partial sums exceed their buffer");
+    if (upd_begin != ctx->upd_wgs)
+        return fail(ctx, GL_EINVAL, "internal: batched update layout of %lld workgroups, "
+                    "launch of %lld", (long long)upd_begin, (long long)ctx->upd_wgs);
     HIP_TRY(ctx, hipMemcpy(ctx->d_batch, tab.data(), tab.size() * sizeof(gl::BatchEntry),
                            hipMemcpyHostToDevice));
     return GL_OK;

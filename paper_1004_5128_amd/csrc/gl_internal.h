@@ -123,6 +123,7 @@ struct BatchEntry {
     double *partial;  // this problem's GEMV partials, up to its split count x P
     double *snap;     // adjoint snapshots: u[k+1] goes to snap[(k+1)/C] when C divides k+1
     int64_t groups;   // this problem's GEMV workgroup target (Problem::gemv_groups)
+    int64_t upd_begin; // first workgroup of this problem in a batched update launch
     int32_t ndim, nx, ny, nz, rxn;
     double r, dt, rate;
 };

@@ -329,19 +329,23 @@ void launch_update(const Problem &pb, const double *u, const double *base, doubl
               p.rxn_rate);
 }
 
-// Batched update: workgroups laid out problem after problem, ceil(P / 256) each.
+// Batched update: workgroups laid out problem after problem, ceil(P / 256) each, problem i
+// from workgroup tab[i].upd_begin on (found by bisection: a handful of scalar loads, where a
+// scan over the table cost each of an ensemble's workgroups up to one load and one 64-bit
+// division per problem before it).
 __global__ __launch_bounds__(256) void update_batched_kernel(const BatchEntry *__restrict__ tab,
                                                              int nprob, int64_t k, int cur,
                                                              int64_t terms, int64_t C) {
-    int64_t w = blockIdx.x;
-    int i = 0;
-    for (; i < nprob; ++i) {
-        const int64_t share = (tab[i].P + 255) / 256;
-        if (w < share) break;
-        w -= share;
+    const int64_t wg = blockIdx.x;
+    int lo = 0, hi = nprob - 1;  // the last problem whose first workgroup is <= wg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].upd_begin <= wg) lo = mid;
+        else hi = mid - 1;
     }
-    if (i >= nprob) return;
-    const BatchEntry &e = tab[i];
+    const BatchEntry &e = tab[lo];
+    const int64_t w = wg - e.upd_begin;
+    if (w >= (e.P + 255) / 256) return;
     const int64_t p = w * 256 + threadIdx.x;
     if (p >= e.P) return;
     const int nsplit = gemv_splits(terms, e.P, e.groups);
