@@ -350,7 +350,8 @@ MODE_RUNS = (("short_L1000", "gemv", {"mode": "short", "L": 1000}),
 def run_memory_modes(w, u_full, oracle_modes):
     """The same workload under short memory (L = 1000 steps; plain and blocked paths) and
     adaptive memory (a = 2, 4, 10, partition reading; plain path): time per solve (one warmup,
-    one timed), history MACs/s and, on the plain path, algorithmic GB/s, the rel-L2
+    one timed, then one more after gl_autotune), history MACs/s and, on the plain path,
+    algorithmic GB/s, the rel-L2
     difference from the full-memory result (the paper's error of a memory mode) and, with the
     oracle, the largest sine-mode error against the oracle's recursion for that mode."""
     import torch
@@ -372,8 +373,18 @@ def run_memory_modes(w, u_full, oracle_modes):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             uT = s.state().cpu().numpy()
+            # the same solve after gl_autotune picked the launch shapes for this schedule
+            s.reset(u0)
+            tuned = s.autotune()
+            s.reset(u0)
+            t0 = time.perf_counter()
+            s.advance(n)
+            torch.cuda.synchronize()
+            dt_tuned = time.perf_counter() - t0
         d = {"path": path, "ms_per_solve": dt * 1e3, "history_macs_per_solve": P * terms,
              "history_macs_per_s": P * terms / dt,
+             "ms_per_solve_autotuned": dt_tuned * 1e3,
+             "autotuned": {"gemv_groups": tuned[0], "product_chunk_wgs": tuned[1]},
              "rel_l2_vs_full_memory": float(np.linalg.norm(uT - u_full) / np.linalg.norm(u_full))}
         if path == "gemv":
             d["algorithmic_gbs"] = 4 * P * (terms - n) / dt / 1e9

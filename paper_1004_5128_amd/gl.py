@@ -148,8 +148,9 @@ def gl_reset(ctx, u0):
 
 
 def gl_autotune(ctx, what=0):
-    """Times candidate launch shapes at step 0 and keeps the fastest; returns (GEMV workgroup
-    target, product workgroups per CU)."""
+    """Before the first step: times candidate launch shapes on the middle step of the run's
+    schedule and keeps the fastest; returns (GEMV workgroup target, product workgroups per
+    CU)."""
     chosen = (C.c_int64 * 2)()
     _check(_lib.gl_autotune(ctx, int(what), chosen), ctx)
     return int(chosen[0]), int(chosen[1])
