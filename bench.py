@@ -732,7 +732,7 @@ def main():
                                                 default_block(W.npoints(w["problem"])))))
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the solver runs on a single "
+        print("bench.py: measures one GPU only (the solver runs on a single "
               "MI355X); --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.adjoint_only:

@@ -62,7 +62,7 @@ typedef int32_t gl_status;
 #define GL_ESTATE (-5)       /* call not valid in the context's current state */
 #define GL_ENONFINITE (-6)   /* a NaN or Inf in the input or in the state */
 #define GL_EHIP (-7)         /* a HIP runtime call failed (message in gl_last_error) */
-#define GL_EUNSUPPORTED (-8) /* valid request that this build does not implement */
+#define GL_EUNSUPPORTED (-8) /* valid request that the library does not implement */
 
 /* Reaction term f(u) (Sec. 2.2, eqs. (18)-(21)). */
 #define GL_RXN_NONE 0   /* f = 0 */
