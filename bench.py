@@ -765,7 +765,9 @@ def main():
     primary = paths[-1]
 
     out_paths = {}
-    traffic = measured_traffic()
+    # the counters were taken on the 256^2 workload (its kernels and launch shapes); other
+    # workloads report traffic as null rather than that ratio
+    traffic = measured_traffic() if args.workload == "2d_256" else {}
     oracle_prefix = oracle_modal = None
     cpu = None
     if not args.no_cpu:
