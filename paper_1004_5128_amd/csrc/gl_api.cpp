@@ -43,6 +43,8 @@ struct gl_ctx {
     double *adj_lamseg = nullptr;  // blocked path: lam[ks .. ke] of a segment, (C + 1) x max P
     double *adj_grad = nullptr;  // per step and workgroup partial dot products, 3 each
     double *adj_fpart = nullptr; // the final reduction's first-stage sums, kAdjFinalParts x 3
+    double *adj_partial2 = nullptr;  // plain path: the recompute's d psi / d gamma partials
+    size_t part_len = 0;         // length of partial (and adj_partial2) in doubles
     gl::Run *adj_runs = nullptr;  // adaptive memory: the transposed schedule's runs
     size_t adj_runs_cap = 0;
     // blocked adjoint (Toeplitz path): the sums over the mu rows before a block of reverse
@@ -365,6 +367,7 @@ gl_status init_impl(gl_ctx *ctx, const gl_problem *probs, int32_t nprob, const d
     HIP_TRY(ctx, hipMemcpy(ctx->d_runs, ctx->sched.runs.data(),
                            ctx->sched.runs.size() * sizeof(gl::Run), hipMemcpyHostToDevice));
     if ((st = dev_alloc(ctx, &ctx->partial, part_len))) return st;
+    ctx->part_len = part_len;
     if ((st = dev_alloc(ctx, &ctx->d_flag, 1))) return st;
 
     if (toep && (st = dev_alloc(ctx, &ctx->tpart, (size_t)std::max<int64_t>(tpart_len, 1))))
@@ -719,15 +722,14 @@ gl_status adjoint_recompute(gl_ctx *ctx, gl::Problem &pb, int64_t ks, int64_t ke
         const int64_t T = ctx->sched.terms[k];
         const int nsplit = gl::gemv_splits(T - 1, P, pb.gemv_groups);
         const bool reverse = ctx->tune.serpentine && (k & 1);
+        // S[k] as the forward formed it, and G[k] = sum over the same terms of
+        // d psi / d gamma (m) delta[k-m] (the m = 0 weight is 0), in one pass over the rows
         if (nsplit > 0)
-            gl::launch_hist_gemv(pb.H, pb.ld, P, pb.psi, ctx->d_runs + rb, nruns, k, 1, T, nsplit,
-                                 reverse, ctx->partial, ctx->stream);
+            gl::launch_hist_gemv_dual(pb.H, pb.ld, P, pb.psi, pb.dpsi, ctx->d_runs + rb, nruns, k,
+                                      1, T, nsplit, reverse, ctx->partial, ctx->adj_partial2,
+                                      ctx->stream);
         gl::launch_update(pb, u, nullptr, un, nullptr, S, ctx->partial, nsplit, ctx->stream);
-        // G[k] = sum over the same terms of d psi / d gamma (m) delta[k-m]; the m = 0 weight is 0
-        if (nsplit > 0)
-            gl::launch_hist_gemv(pb.H, pb.ld, P, pb.dpsi, ctx->d_runs + rb, nruns, k, 1, T, nsplit,
-                                 false, ctx->partial, ctx->stream);
-        gl::launch_reduce_partials(ctx->partial, nsplit, P, nullptr, ctx->adj_G + i * P,
+        gl::launch_reduce_partials(ctx->adj_partial2, nsplit, P, nullptr, ctx->adj_G + i * P,
                                    ctx->stream);
     }
     if (toep) {
@@ -761,6 +763,7 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
     size_t need = ((size_t)n * ctx->maxld) * sizeof(float) +
                   ((size_t)(3 * C + 1) * ctx->maxP + 2 * (size_t)ctx->maxP +
                    (size_t)n * groups * 3 + 3 * gl::kAdjFinalParts) * sizeof(double);
+    if (!toep) need += ctx->part_len * sizeof(double);
     if (toep) {
         need += (2 * (size_t)ctx->B + ctx->B2 + C + 1 + 2 * gl::kMaxFuse) * ctx->maxP *
                 sizeof(double);
@@ -780,6 +783,7 @@ gl_status adjoint_alloc(gl_ctx *ctx) {
     if ((st = dev_alloc(ctx, &ctx->adj_lam[1], ctx->maxP))) return st;
     if ((st = dev_alloc(ctx, &ctx->adj_grad, (size_t)n * groups * 3))) return st;
     if ((st = dev_alloc(ctx, &ctx->adj_fpart, (size_t)gl::kAdjFinalParts * 3))) return st;
+    if (!toep && (st = dev_alloc(ctx, &ctx->adj_partial2, ctx->part_len))) return st;
     if (toep) {
         if ((st = dev_alloc(ctx, &ctx->adj_oldA, (size_t)ctx->B * ctx->maxP))) return st;
         if ((st = dev_alloc(ctx, &ctx->adj_oldG, (size_t)ctx->B * ctx->maxP))) return st;

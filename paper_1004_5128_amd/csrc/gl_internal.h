@@ -112,6 +112,12 @@ constexpr int kMaxSplits = 64;
 void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, const Run *runs,
                       int nruns, int64_t k, int64_t t_begin, int64_t t_end, int nsplit,
                       bool reverse, double *partial, hipStream_t s);
+// The same launch with a second weight table psi2 over the same rows: partial receives
+// exactly what launch_hist_gemv writes, partial2 (same layout) the sums with psi2.
+void launch_hist_gemv_dual(const float *H, int64_t ld, int64_t P, const double *psi,
+                           const double *psi2, const Run *runs, int nruns, int64_t k,
+                           int64_t t_begin, int64_t t_end, int nsplit, bool reverse,
+                           double *partial, double *partial2, hipStream_t s);
 
 // One problem of a batched (ensemble) launch; a device-resident table, one entry per
 // problem, built at gl_init.

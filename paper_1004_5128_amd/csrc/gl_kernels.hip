@@ -59,12 +59,17 @@ constexpr int kGemvUnroll = 8;
 
 // Terms [ta, tb) of the step-k schedule for the four points col..col+3 (col < P):
 // returns their FP64 sums in a[0..3].
+// kDual: also the sum with a second weight table psi2 over the same rows (the adjoint's
+// d psi / d gamma sums), into b; the first sum's operations are the same either way.
+template <bool kDual>
 __device__ __forceinline__ void gemv_points(const GL_GLOBAL float *__restrict__ H, int64_t ld,
                                             const GL_CONST double *__restrict__ psi,
+                                            const GL_CONST double *__restrict__ psi2,
                                             const GL_CONST Run *__restrict__ runs, int nruns,
                                             int64_t k, int64_t ta, int64_t tb, int64_t col,
-                                            int reverse, double a[4]) {
+                                            int reverse, double a[4], double b[4]) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
     // Runs are visited in order; with `reverse` the terms are walked from the last to the
     // first (oldest row first), so that consecutive steps can traverse the history in
     // opposite directions.
@@ -107,6 +112,16 @@ __device__ __forceinline__ void gemv_points(const GL_GLOBAL float *__restrict__ 
                     a2 = fma(w[u], (double)v[u].z, a2);
                     a3 = fma(w[u], (double)v[u].w, a3);
                 }
+                if constexpr (kDual) {
+#pragma unroll
+                    for (int u = 0; u < kGemvUnroll; ++u) {
+                        const double w2 = coef * psi2[m + u * stride];
+                        b0 = fma(w2, (double)v[u].x, b0);
+                        b1 = fma(w2, (double)v[u].y, b1);
+                        b2 = fma(w2, (double)v[u].z, b2);
+                        b3 = fma(w2, (double)v[u].w, b3);
+                    }
+                }
                 row -= kGemvUnroll * step;
                 m += kGemvUnroll * stride;
                 cnt -= kGemvUnroll;
@@ -118,6 +133,13 @@ __device__ __forceinline__ void gemv_points(const GL_GLOBAL float *__restrict__ 
                 a1 = fma(w, (double)v.y, a1);
                 a2 = fma(w, (double)v.z, a2);
                 a3 = fma(w, (double)v.w, a3);
+                if constexpr (kDual) {
+                    const double w2 = coef * psi2[m];
+                    b0 = fma(w2, (double)v.x, b0);
+                    b1 = fma(w2, (double)v.y, b1);
+                    b2 = fma(w2, (double)v.z, b2);
+                    b3 = fma(w2, (double)v.w, b3);
+                }
                 row -= step;
                 m += stride;
             }
@@ -128,6 +150,12 @@ __device__ __forceinline__ void gemv_points(const GL_GLOBAL float *__restrict__ 
     a[1] = a1;
     a[2] = a2;
     a[3] = a3;
+    if constexpr (kDual) {
+        b[0] = b0;
+        b[1] = b1;
+        b[2] = b2;
+        b[3] = b3;
+    }
 }
 
 // Split s of nsplit covers terms [t_begin + T s / nsplit, t_begin + T (s+1) / nsplit).
@@ -155,9 +183,28 @@ __global__ __launch_bounds__(kGemvThreads) void hist_gemv_kernel(
     int64_t ta, tb;
     gemv_split_range(t_begin, t_end, blockIdx.y, gridDim.y, &ta, &tb);
     double a[4];
-    gemv_points((const GL_GLOBAL float *)H, ld, (const GL_CONST double *)psi,
-                (const GL_CONST Run *)runs, nruns, k, ta, tb, col, reverse, a);
+    gemv_points<false>((const GL_GLOBAL float *)H, ld, (const GL_CONST double *)psi, nullptr,
+                       (const GL_CONST Run *)runs, nruns, k, ta, tb, col, reverse, a, nullptr);
     store4((GL_GLOBAL double *)partial + (int64_t)blockIdx.y * P + col, col, P, a);
+}
+
+// Both sums of the adjoint's recomputation (psi and d psi / d gamma) in one pass over the
+// history rows: partial receives exactly what hist_gemv_kernel writes, partial2 the second.
+__global__ __launch_bounds__(kGemvThreads) void hist_gemv_dual_kernel(
+    const float *__restrict__ H, int64_t ld, int64_t P, const double *__restrict__ psi,
+    const double *__restrict__ psi2, const Run *__restrict__ runs, int nruns, int64_t k,
+    int64_t t_begin, int64_t t_end, int reverse, double *__restrict__ partial,
+    double *__restrict__ partial2) {
+    const int64_t col = ((int64_t)blockIdx.x * kGemvThreads + threadIdx.x) * 4;
+    if (col >= P) return;
+    int64_t ta, tb;
+    gemv_split_range(t_begin, t_end, blockIdx.y, gridDim.y, &ta, &tb);
+    double a[4], b[4];
+    gemv_points<true>((const GL_GLOBAL float *)H, ld, (const GL_CONST double *)psi,
+                      (const GL_CONST double *)psi2, (const GL_CONST Run *)runs, nruns, k, ta, tb,
+                      col, reverse, a, b);
+    store4((GL_GLOBAL double *)partial + (int64_t)blockIdx.y * P + col, col, P, a);
+    store4((GL_GLOBAL double *)partial2 + (int64_t)blockIdx.y * P + col, col, P, b);
 }
 
 __host__ __device__ int gemv_splits(int64_t terms, int64_t P, int64_t target_groups) {
@@ -178,6 +225,16 @@ void launch_hist_gemv(const float *H, int64_t ld, int64_t P, const double *psi, 
     const unsigned colblocks = (unsigned)((P + kGemvCols - 1) / kGemvCols);
     GL_LAUNCH(hist_gemv_kernel, dim3(colblocks, (unsigned)nsplit), dim3(kGemvThreads), 0, s, H, ld,
               P, psi, runs, nruns, k, t_begin, t_end, reverse ? 1 : 0, partial);
+}
+
+void launch_hist_gemv_dual(const float *H, int64_t ld, int64_t P, const double *psi,
+                           const double *psi2, const Run *runs, int nruns, int64_t k,
+                           int64_t t_begin, int64_t t_end, int nsplit, bool reverse,
+                           double *partial, double *partial2, hipStream_t s) {
+    const unsigned colblocks = (unsigned)((P + kGemvCols - 1) / kGemvCols);
+    GL_LAUNCH(hist_gemv_dual_kernel, dim3(colblocks, (unsigned)nsplit), dim3(kGemvThreads), 0, s,
+              H, ld, P, psi, psi2, runs, nruns, k, t_begin, t_end, reverse ? 1 : 0, partial,
+              partial2);
 }
 
 // ---- batched over the problems of an ensemble: one launch for every problem's GEMV.
@@ -205,8 +262,9 @@ __global__ __launch_bounds__(kGemvThreads) void hist_gemv_batched_kernel(
     int64_t ta, tb;
     gemv_split_range(t_begin, t_end, split, nsplit, &ta, &tb);
     double a[4];
-    gemv_points((const GL_GLOBAL float *)e.H, e.ld, (const GL_CONST double *)e.psi,
-                (const GL_CONST Run *)runs, nruns, k, ta, tb, col, reverse, a);
+    gemv_points<false>((const GL_GLOBAL float *)e.H, e.ld, (const GL_CONST double *)e.psi,
+                       nullptr, (const GL_CONST Run *)runs, nruns, k, ta, tb, col, reverse, a,
+                       nullptr);
     store4((GL_GLOBAL double *)e.partial + (int64_t)split * e.P + col, col, e.P, a);
 }
 
