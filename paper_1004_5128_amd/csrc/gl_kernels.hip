@@ -288,7 +288,15 @@ __global__ void reduce_partials_kernel(const double *__restrict__ partial, int n
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     double acc = base ? base[p] : 0.0;
-    for (int q = 0; q < nsplit; ++q) acc += partial[(int64_t)q * P + p];
+    int q = 0;
+    for (; q + 8 <= nsplit; q += 8) {  // loads issued eight at a time, added in split order
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = partial[(int64_t)(q + i) * P + p];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc += v[i];
+    }
+    for (; q < nsplit; ++q) acc += partial[(int64_t)q * P + p];
     S[p] = acc;
 }
 
